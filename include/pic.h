@@ -1,0 +1,253 @@
+/*
+ * libpic — explicit 1D3V electrostatic PIC/MCC of an RF capacitively coupled
+ * argon discharge on one MI355X (gfx950), behind a plain C ABI.
+ *
+ * The method is the six-step cycle of Vass, Palla & Hartmann,
+ * "Revisiting the numerical stability/accuracy conditions of explicit
+ * PIC/MCC simulations of low-temperature gas discharges" (arXiv:2109.04469),
+ * Sec. 2 (computational method) with the surface model of Sec. 2 step 5 and
+ * the collision step of Sec. 2 step 6; the problem parameters are those of
+ * Sec. 3, Table 1.
+ *
+ * Conventions for every entry point below
+ *  - Return value: int32 status, PIC_OK (0) or one of the negative PIC_E*
+ *    codes. No C++ exception or longjmp crosses this boundary.
+ *  - Memory: libpic never allocates or frees device memory. The caller
+ *    allocates ONE device workspace of the size pic_workspace_bytes() reports
+ *    and keeps it alive until pic_free(). Host metadata (the handle) is
+ *    malloc'd by pic_init and released by pic_free.
+ *  - Streams: every device operation is enqueued on the hipStream_t given to
+ *    pic_init (NULL = the legacy default stream). pic_step is asynchronous;
+ *    the calls documented as "synchronises" wait for that stream.
+ *  - Errors found on the device (non-finite state, capacity overflow, speed
+ *    beyond a collision table) are latched in a device error word and
+ *    returned by the next synchronising call. After a latched error the
+ *    particle state is unspecified; recover with pic_set_state.
+ *  - A handle may be used by one host thread at a time.
+ *  - Units: SI unless the name says otherwise (_ev = electronvolt).
+ */
+#ifndef LIBPIC_PIC_H
+#define LIBPIC_PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PIC_OK          0
+#define PIC_EINVAL     -1 /* bad argument or parameter set                    */
+#define PIC_EHIP       -2 /* a HIP runtime call failed (no GPU, launch error) */
+#define PIC_ECAPACITY  -3 /* a species outgrew its capacity                   */
+#define PIC_EUNSTABLE  -4 /* a non-finite position, velocity or field value   */
+#define PIC_ETABLE     -5 /* a collision candidate's speed is beyond its table */
+#define PIC_ESTATE     -6 /* call not valid in the handle's current state     */
+
+/* ---- species ----------------------------------------------------------- */
+#define PIC_ELECTRON 0
+#define PIC_ION      1 /* Ar+ */
+
+/* ---- test-mode flags (pic_params.flags) --------------------------------- */
+#define PIC_FLAG_NO_FIELD       (1u << 0) /* E = 0 everywhere, no Poisson solve */
+#define PIC_FLAG_FIXED_E        (1u << 1) /* E held at the array of pic_set_field */
+#define PIC_FLAG_NO_COLL        (1u << 2) /* skip the collision step            */
+#define PIC_FLAG_IMMOBILE_IONS  (1u << 3) /* ions never pushed nor collided     */
+#define PIC_FLAG_RECORD         (1u << 4) /* keep per-slot decision codes       */
+#define PIC_FLAG_THOMAS         (1u << 5) /* solve Poisson with the serial Thomas
+                                             recurrence instead of the exact
+                                             integer prefix-sum form           */
+
+/* ---- event counters (pic_get_counters), accumulated since pic_set_state --- */
+enum {
+  PIC_CNT_STEPS = 0,
+  PIC_CNT_E_PUSHED,      /* electron particle-steps                          */
+  PIC_CNT_I_PUSHED,      /* ion particle-steps (sub-cycled steps only)       */
+  PIC_CNT_E_ABSORBED,
+  PIC_CNT_E_REFLECTED,
+  PIC_CNT_I_ABSORBED,
+  PIC_CNT_SE_EMITTED,
+  PIC_CNT_E_CANDIDATES,  /* null-collision candidates                        */
+  PIC_CNT_E_ELASTIC,
+  PIC_CNT_E_EXCITATION,
+  PIC_CNT_E_IONIZATION,
+  PIC_CNT_I_CANDIDATES,
+  PIC_CNT_I_ISOTROPIC,
+  PIC_CNT_I_BACKWARD,
+  PIC_CNT_REFLECT_LOST,  /* reflected but still outside: removed             */
+  PIC_CNT_RESERVED,
+  PIC_NCOUNTERS
+};
+
+/* ---- per-slot decision code (pic_get_decisions), one byte per slot ------
+ * bits 0..2  wall outcome: 0 inside, 1 absorbed, 2 reflected,
+ *            3 absorbed and emitted a secondary electron, 4 reflected but
+ *            still outside (removed)
+ * bits 3..5  collision: 0 not a candidate, 1 null, 2 first process
+ *            (e: elastic, Ar+: isotropic), 3 second (e: excitation,
+ *            Ar+: backward), 4 third (e: ionization)
+ * bit  7     slot was pushed this step                                      */
+
+typedef struct pic_params {
+  /* discharge (Sec. 2 and Table 1) */
+  double   gap_m;            /* L, electrode gap                               */
+  double   pressure_pa;      /* p                                              */
+  double   gas_temp_k;       /* T_g                                            */
+  double   rf_voltage_v;     /* phi_0: V(t) = phi_0 cos(2 pi f t) on x = 0     */
+  double   rf_freq_hz;       /* f                                              */
+  int32_t  steps_per_cycle;  /* N_t: dt = 1/(f N_t)                            */
+  int32_t  n_cells;          /* N_x - 1: dx = L/n_cells, N_x grid points       */
+  double   weight;           /* W, real particles per superparticle            */
+  double   area_m2;          /* nominal electrode area (1 cm^2 in the paper)   */
+  double   reflection;       /* R, electron reflection probability            */
+  double   gamma_see;        /* gamma, secondary emission yield per ion impact */
+  double   see_temp_ev;      /* temperature of emitted secondary electrons     */
+  /* capacities and schedule */
+  int64_t  capacity[2];      /* max superparticles per species (e, Ar+)        */
+  int32_t  ion_subcycle;     /* k >= 1: ions advance on steps n % k == 0 with k dt */
+  int32_t  sort_interval;    /* cell sort after every K-th step (0 = never)    */
+  /* counter-based random streams: key = (seed, run) */
+  uint32_t seed;
+  uint32_t run;
+  /* diagnostics (Sec. 3.1: EEPF at the discharge centre) */
+  int32_t  eepf_bins;        /* >= 1                                           */
+  double   eepf_emax_ev;     /* histogram covers [0, eepf_emax_ev)             */
+  double   eepf_halfwidth_m; /* electrons with |x - L/2| <= halfwidth count    */
+  uint32_t flags;            /* PIC_FLAG_*                                     */
+} pic_params;
+
+/* Collision cross sections (Sec. 2 step 6), host arrays in m^2, tabulated at
+ * the speeds v_k = k * dv for k = 0..n-1. Electron tables are indexed by the
+ * electron speed, ion tables by the ion-atom relative speed (lab energy
+ * 1/2 M g^2). Copied at pic_init; the caller keeps ownership. */
+typedef struct pic_xsec {
+  int32_t        n;                 /* entries per table, >= 2               */
+  double         dv_e;              /* electron table speed step, m/s        */
+  double         dv_i;              /* ion table speed step, m/s             */
+  const double*  sigma_e[3];        /* elastic, excitation, ionization       */
+  const double*  sigma_i[2];        /* isotropic elastic, backward (charge transfer) */
+  double         exc_threshold_ev;  /* energy lost in excitation             */
+  double         ion_threshold_ev;  /* energy lost in ionization             */
+} pic_xsec;
+
+/* Quantities derived at pic_init (host), for inspection. */
+typedef struct pic_derived {
+  int32_t n_x;          /* grid points                                      */
+  int32_t n_tiles_max;  /* particle tiles at full capacity (largest species) */
+  double  dx;           /* L/(N_x - 1)                                      */
+  double  dt;           /* 1/(f N_t)                                        */
+  double  gas_density;  /* p/(k_B T_g)                                      */
+  double  nu_max[2];    /* max total collision frequency per species, 1/s   */
+  double  p_coll[2];    /* 1 - exp(-nu_max dt_s), Sec. 3.5                  */
+} pic_derived;
+
+/* Time-averaged moments (Sec. 3.1). Host arrays owned by the caller; any
+ * pointer may be NULL to skip that output. */
+typedef struct pic_moments_out {
+  double*  n_e;           /* [N_x] electron density, m^-3                   */
+  double*  n_i;           /* [N_x] ion density, m^-3                        */
+  double*  mean_energy_e; /* [N_x] CIC-weighted mean electron energy, eV    */
+  double*  eepf;          /* [eepf_bins] EEPF at L/2, eV^-3/2, normalised so
+                             that sum_b sqrt(eps_b) f_b d(eps) = 1          */
+  int64_t  steps_averaged;
+} pic_moments_out;
+
+typedef struct pic_handle pic_handle;
+
+/* Size of the single device workspace for parameter set *p (capacities, grid,
+ * tables). Returns PIC_EINVAL for an invalid parameter set. */
+int pic_workspace_bytes(const pic_params* p, const pic_xsec* xs, uint64_t* bytes);
+
+/* Validates *p and *xs, derives dx, dt, gas density, the cumulative
+ * collision-frequency tables and P_coll per species (Sec. 2, Sec. 3.5),
+ * builds the RF voltage table V_n = phi_0 cos(2 pi n / N_t), lays out the
+ * caller's device workspace (at least pic_workspace_bytes, 256-byte aligned)
+ * and zeroes it. Both species start empty at step 0. stream is a
+ * hipStream_t. Synchronises. On success *out owns host metadata only. */
+int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace,
+             uint64_t workspace_bytes, void* stream, pic_handle** out);
+
+/* Replaces the particles of one species with n superparticles: positions x
+ * in [0, L] and velocities (vx, vy, vz) taken as v at the half step before
+ * `step` (leap-frog staggering, Sec. 2 step 4). Arrays are SoA of n doubles,
+ * host or device pointers (the copy direction is inferred). Sets the step
+ * counter of the handle to `step` for both species, clears the event
+ * counters and latched errors, and recomputes the charge deposit of both
+ * species. Synchronises. PIC_ECAPACITY if n > capacity. */
+int pic_set_state(pic_handle* h, int species, const double* x, const double* vx,
+                  const double* vy, const double* vz, int64_t n, int64_t step);
+
+/* Copies the current particles of one species into caller arrays of
+ * `cap` doubles each (host or device). *n receives the count; if the count
+ * exceeds cap nothing is copied and PIC_ECAPACITY is returned. *step (may be
+ * NULL) receives the step counter. Synchronises and reports latched errors. */
+int pic_get_state(pic_handle* h, int species, double* x, double* vx, double* vy,
+                  double* vz, int64_t cap, int64_t* n, int64_t* step);
+
+/* Enqueues n_steps steps of the cycle of Sec. 2: deposit (1), Poisson with
+ * Dirichlet walls phi(0) = V(t), phi(L) = 0 and field (2), gather (3),
+ * leap-frog push (4), wall absorption / reflection / secondary emission (5),
+ * null-collision MCC (6); survivors compacted in slot order, births appended;
+ * cell sort every sort_interval steps. Asynchronous: returns after enqueueing;
+ * errors of earlier steps are reported by the next synchronising call. */
+int pic_step(pic_handle* h, int64_t n_steps);
+
+/* Waits for the stream and returns the first latched device error, if any. */
+int pic_sync(pic_handle* h);
+
+/* Sets the field used by PIC_FLAG_FIXED_E runs: N_x doubles (host or
+ * device), V/m. Synchronises. PIC_ESTATE if the flag is not set. */
+int pic_set_field(pic_handle* h, const double* E);
+
+/* Copies the charge density rho, potential phi and field E of the most
+ * recent field solve (N_x doubles each, host or device; NULL skips; under
+ * PIC_FLAG_NO_FIELD or PIC_FLAG_FIXED_E phi is 0) and the integer CIC
+ * deposits of the current particles of both species, i.e. the input of the
+ * next solve (N_x int64 each, units of 2^-32 superparticle; NULL skips).
+ * Synchronises. */
+int pic_get_field(pic_handle* h, double* rho, double* phi, double* E,
+                  int64_t* deposit_e, int64_t* deposit_i);
+
+/* Starts (on != 0) or stops accumulation of the time-averaged moments. Each
+ * step taken while on contributes its densities at the start of the step and
+ * the electron energies from the half-step velocities. */
+int pic_measure(pic_handle* h, int on);
+
+/* Reads the time-averaged moments; reset != 0 clears the accumulators
+ * afterwards. Synchronises. */
+int pic_moments(pic_handle* h, pic_moments_out* out, int reset);
+
+/* Copies the PIC_NCOUNTERS event counters (host int64 array). Synchronises. */
+int pic_get_counters(pic_handle* h, int64_t* counters);
+
+/* With PIC_FLAG_RECORD: copies the decision codes of the last step for the
+ * slots that existed at its start (host or device buffer of `cap` bytes).
+ * *n receives the number of slots. Synchronises. */
+int pic_get_decisions(pic_handle* h, int species, uint8_t* codes, int64_t cap, int64_t* n);
+
+/* Copies the derived quantities of pic_init (host). */
+int pic_get_derived(const pic_handle* h, pic_derived* d);
+
+/* Releases host metadata. The workspace stays the caller's. Waits for the
+ * stream first. NULL is ignored. */
+void pic_free(pic_handle* h);
+
+/* Static string describing a status code. */
+const char* pic_strerror(int status);
+
+/* ---- self-checks of device arithmetic (test surface) ---------------------
+ * Philox4x32-10 (Salmon et al., SC'11) evaluated on the device for n
+ * counters: ctr is 4n uint32 (host), key 2 uint32 (host), out 4n uint32
+ * (host). The method's random decisions (Sec. 2 steps 5 and 6) draw from
+ * this generator keyed by (seed, run) with counter (step, slot,
+ * 16*species + purpose, 0). Synchronises on the null stream. */
+int pic_selftest_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n);
+
+/* Correctly rounded FP64 square root on the device for n host doubles. */
+int pic_selftest_sqrt(const double* in, double* out, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBPIC_PIC_H */

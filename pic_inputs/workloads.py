@@ -1,0 +1,101 @@
+"""Named synthetic discharge workloads (plain parameter dictionaries).
+
+The field names are those of the library's parameter block; the oracle's
+wrapper reads the same dictionaries. Values follow the paper's problem
+statement (arXiv:2109.04469, Sec. 2 and Table 1): a 13.56 MHz single-frequency
+drive on one electrode of a plane-parallel argon gap with a 1 cm^2 nominal
+area, a uniform superparticle weight, reflection R and emission yield gamma.
+
+Readings fixed here:
+  * "cells" = N_x - 1, so the grid has n_cells + 1 points.
+  * Weights are chosen so that the initial uniform plasma of density n0 holds
+    the stated number of superparticles per species: W = n0 * A * L / N.
+"""
+from __future__ import annotations
+
+import copy
+
+RF_FREQ = 13.56e6
+AREA = 1e-4  # 1 cm^2 (Sec. 3)
+
+_BASE = dict(
+    gap_m=0.025,
+    pressure_pa=10.0,
+    gas_temp_k=300.0,
+    rf_voltage_v=100.0,
+    rf_freq_hz=RF_FREQ,
+    steps_per_cycle=1000,
+    n_cells=128,
+    weight=2.5e5,
+    area_m2=AREA,
+    reflection=0.0,
+    gamma_see=0.0,
+    see_temp_ev=1.0,
+    capacity=(40_000, 40_000),
+    ion_subcycle=1,
+    sort_interval=25,
+    seed=1,
+    run=1,
+    eepf_bins=128,
+    eepf_emax_ev=32.0,
+    eepf_halfwidth_m=0.05 * 0.025,
+    flags=0,
+)
+
+
+def _mk(**kw):
+    p = copy.deepcopy(_BASE)
+    p.update(kw)
+    p["eepf_halfwidth_m"] = kw.get("eepf_halfwidth_m", 0.05 * p["gap_m"])
+    return p
+
+
+# Small case: 2.5 cm, 128 cells, 100 V, 10 Pa, dt = T_RF/1000,
+# 10k + 10k particles (n0 = 1e15 m^-3), gamma = 0, R = 0.2, 10 RF cycles.
+C1 = dict(
+    name="c1_small",
+    params=_mk(gap_m=0.025, n_cells=128, steps_per_cycle=1000, rf_voltage_v=100.0,
+               pressure_pa=10.0, weight=2.5e5, reflection=0.2, gamma_see=0.0,
+               capacity=(40_000, 40_000), ion_subcycle=1, run=1),
+    n_init=(10_000, 10_000), t_init_ev=(2.0, 0.03), cycles=10,
+)
+
+# Production size: 2.5 cm, 512 cells, dt = T_RF/4000, 300 V, 50 Pa,
+# 400k + 400k particles (n0 = 1e16 m^-3), gamma = 0.1, R = 0, 200 RF cycles.
+C2 = dict(
+    name="c2_production",
+    params=_mk(gap_m=0.025, n_cells=512, steps_per_cycle=4000, rf_voltage_v=300.0,
+               pressure_pa=50.0, weight=6.25e4, reflection=0.0, gamma_see=0.1,
+               capacity=(1_600_000, 1_600_000), ion_subcycle=1, run=2),
+    n_init=(400_000, 400_000), t_init_ev=(2.0, 0.03), cycles=200,
+)
+
+# Large low-pressure case: 6.7 cm, 2048 cells, dt = T_RF/8000, 2 Pa, 500 V,
+# gamma = 0.2, R = 0.5, 4M + 4M particles (n0 = 5e15 m^-3, W = 8375),
+# ions sub-cycled x10, 100 RF cycles.
+C3 = dict(
+    name="c3_large_lowp",
+    params=_mk(gap_m=0.067, n_cells=2048, steps_per_cycle=8000, rf_voltage_v=500.0,
+               pressure_pa=2.0, weight=8375.0, reflection=0.5, gamma_see=0.2,
+               capacity=(16_000_000, 16_000_000), ion_subcycle=10, run=3),
+    n_init=(4_000_000, 4_000_000), t_init_ev=(2.0, 0.03), cycles=100,
+)
+
+WORKLOADS = {w["name"]: w for w in (C1, C2, C3)}
+
+
+def get(name):
+    return copy.deepcopy(WORKLOADS[name])
+
+
+def scaled(workload, n_per_species, capacity_factor=4):
+    """Same discharge with a different superparticle count: the weight is
+    rescaled so the initial density is unchanged."""
+    w = copy.deepcopy(workload)
+    ne, ni = w["n_init"]
+    f = ne / float(n_per_species)
+    w["params"]["weight"] = w["params"]["weight"] * f
+    w["n_init"] = (int(n_per_species), int(round(ni / f)))
+    cap = int(max(64, capacity_factor * max(w["n_init"])))
+    w["params"]["capacity"] = (cap, cap)
+    return w
