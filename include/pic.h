@@ -238,14 +238,17 @@ const char* pic_strerror(int status);
 
 /* ---- self-checks of device arithmetic (test surface) ---------------------
  * Philox4x32-10 (Salmon et al., SC'11) evaluated on the device for n
- * counters: ctr is 4n uint32 (host), key 2 uint32 (host), out 4n uint32
- * (host). The method's random decisions (Sec. 2 steps 5 and 6) draw from
+ * counters: ctr and out are device arrays of 4n uint32, key is 2 host
+ * uint32. The method's random decisions (Sec. 2 steps 5 and 6) draw from
  * this generator keyed by (seed, run) with counter (step, slot,
- * 16*species + purpose, 0). Synchronises on the null stream. */
-int pic_selftest_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n);
+ * 16*species + purpose, 0). Runs on `stream` (a hipStream_t) and
+ * synchronises it. */
+int pic_selftest_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
+                        void* stream);
 
-/* Correctly rounded FP64 square root on the device for n host doubles. */
-int pic_selftest_sqrt(const double* in, double* out, int64_t n);
+/* FP64 square root of n device doubles on the device (the wall and
+ * collision decisions rely on it being correctly rounded). Synchronises. */
+int pic_selftest_sqrt(const double* in, double* out, int64_t n, void* stream);
 
 #ifdef __cplusplus
 }

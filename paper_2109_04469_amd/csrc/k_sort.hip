@@ -1,0 +1,136 @@
+// Periodic cell sort: a stable counting sort of one species by cell index
+// j = clamp(floor(x / dx), 0, N_x - 2), which keeps the particles of a tile in
+// a few neighbouring cells so the particle kernel's deposit flush and its
+// field gathers stay local. Stable, so the result is a pure function of the
+// input order. Three kernels:
+//   count   per-chunk key histograms (LDS), written key-major
+//   scan    exclusive scan over (key, chunk) -> output offsets
+//   scatter each chunk walks its particles in order; lanes with equal keys
+//           are ranked with wave ballots and the waves of a workgroup take
+//           their offsets in turn, which preserves the input order.
+#include "pic_internal.h"
+
+namespace pic {
+
+constexpr int kSortThreads = 256;
+constexpr int kScanThreads = 1024;
+
+__device__ __forceinline__ void chunk_range(int64_t n, int nblocks, int b, int64_t& lo,
+                                            int64_t& hi) {
+  const int64_t chunk = (n + nblocks - 1) / nblocks;
+  lo = (int64_t)b * chunk;
+  hi = lo + chunk;
+  if (hi > n) hi = n;
+  if (lo > n) lo = n;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_count(SortArgs a) {
+  extern __shared__ uint32_t sh[];
+  const int nkeys = a.nx - 1;
+  for (int k = threadIdx.x; k < nkeys; k += kSortThreads) sh[k] = 0u;
+  __syncthreads();
+  int64_t lo, hi;
+  chunk_range(min(*a.count, a.cap), a.nblocks, blockIdx.x, lo, hi);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads)
+    atomicAdd(&sh[cell_key(a.src[0][i], a.inv_dx, a.nx)], 1u);
+  __syncthreads();
+  for (int k = threadIdx.x; k < nkeys; k += kSortThreads)
+    a.cnt[(size_t)k * a.nblocks + blockIdx.x] = sh[k];
+}
+
+// Exclusive scan of total = nkeys * nblocks counters, in place, one
+// workgroup: each wave owns a contiguous segment read 64 entries at a time.
+__global__ __launch_bounds__(kScanThreads) void k_sort_scan(SortArgs a) {
+  __shared__ uint32_t s_wave[kScanThreads / kWave + 1];
+  const int64_t total = (int64_t)(a.nx - 1) * a.nblocks;
+  const int nw = kScanThreads / kWave;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t seg = ((total + nw - 1) / nw + kWave - 1) / kWave * kWave;
+  const int64_t lo = (int64_t)wave * seg;
+  int64_t hi = lo + seg;
+  if (hi > total) hi = total;
+  uint32_t sum = 0;
+  for (int64_t i = lo + lane; i < hi; i += kWave) sum += a.cnt[i];
+  sum = wave_sum<unsigned int>(sum);
+  if (lane == 0) s_wave[wave] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < nw; ++w) {
+      const uint32_t v = s_wave[w];
+      s_wave[w] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  uint32_t run = s_wave[wave];
+  for (int64_t i0 = lo; i0 < hi; i0 += kWave) {
+    const int64_t i = i0 + lane;
+    const uint32_t v = i < hi ? a.cnt[i] : 0u;
+    const uint32_t inc = wave_incl_scan<unsigned int>(v);
+    if (i < hi) a.cnt[i] = run + inc - v;
+    run += __shfl(inc, kWave - 1, kWave);
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs a) {
+  extern __shared__ uint32_t off[];
+  __shared__ uint32_t s_base[kSortThreads / kWave][kWave];
+  const int nkeys = a.nx - 1;
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int k = threadIdx.x; k < nkeys; k += kSortThreads)
+    off[k] = a.cnt[(size_t)k * a.nblocks + blockIdx.x];
+  __syncthreads();
+  int64_t lo, hi;
+  chunk_range(min(uniform64(*a.count), a.cap), a.nblocks, blockIdx.x, lo, hi);
+  lo = uniform64(lo);
+  hi = uniform64(hi);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  for (int64_t b0 = lo; b0 < hi; b0 += kSortThreads) {
+    const int64_t i = b0 + threadIdx.x;
+    const bool valid = i < hi;
+    double v[4];
+    int key = 0;
+    if (valid) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] = a.src[q][i];
+      key = cell_key(v[0], a.inv_dx, a.nx);
+    }
+    // lanes of this wave holding the same key
+    uint64_t mask = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 13; ++bit) {
+      const bool on = (key >> bit) & 1;
+      const uint64_t bm = __ballot(valid && on);
+      mask &= on ? bm : ~bm;
+    }
+    const int rank = __popcll(mask & lt);
+    const int leader = __ffsll((long long)mask) - 1;
+    for (int w = 0; w < kSortThreads / kWave; ++w) {
+      if (wave == w && valid && lane == leader) {
+        const uint32_t bse = off[key];
+        off[key] = bse + (uint32_t)__popcll(mask);
+        s_base[w][lane] = bse;
+      }
+      __syncthreads();
+    }
+    if (valid) {
+      const uint32_t dest = s_base[wave][leader] + (uint32_t)rank;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a.dst[q][dest] = v[q];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_sort(const SortArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)(a.nx - 1) * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_sort_count, dim3(a.nblocks), dim3(kSortThreads), lds, s, a);
+  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kScanThreads), 0, s, a);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(a.nblocks), dim3(kSortThreads), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace pic

@@ -1,0 +1,641 @@
+// libpic C ABI: parameter validation, derived constants, workspace layout
+// and the per-step launch schedule. Host code only; every step of the method
+// runs in the kernels of k_field / k_particle / k_sort.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pic_internal.h"
+
+using namespace pic;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxCells = 4096;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t ctl, part[2][2][4], codes[2], tstat[2], dep_e[2], dep_i[2], rho, phi, E, cum[2], th_cp,
+      th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, sort_cnt, total;
+  int64_t max_tiles[2];
+  int sort_blocks;
+};
+
+int validate(const pic_params* p, const pic_xsec* xs) {
+  if (!p || !xs) return PIC_EINVAL;
+  if (!(p->gap_m > 0) || !(p->rf_freq_hz > 0) || p->steps_per_cycle < 1) return PIC_EINVAL;
+  if (p->n_cells < 2 || p->n_cells > kMaxCells) return PIC_EINVAL;
+  if (!(p->weight > 0) || !(p->area_m2 > 0) || !(p->gas_temp_k > 0) || !(p->pressure_pa >= 0))
+    return PIC_EINVAL;
+  if (!(p->reflection >= 0 && p->reflection <= 1) || !(p->gamma_see >= 0 && p->gamma_see <= 1))
+    return PIC_EINVAL;
+  if (!(p->see_temp_ev >= 0)) return PIC_EINVAL;
+  for (int s = 0; s < 2; ++s)
+    if (p->capacity[s] < 0 || p->capacity[s] > ((int64_t)1 << 31) - kTile) return PIC_EINVAL;
+  if (p->ion_subcycle < 1 || p->sort_interval < 0) return PIC_EINVAL;
+  if (p->eepf_bins < 1 || p->eepf_bins > 4096 || !(p->eepf_emax_ev > 0) ||
+      !(p->eepf_halfwidth_m >= 0))
+    return PIC_EINVAL;
+  if (xs->n < 2 || !(xs->dv_e > 0) || !(xs->dv_i > 0)) return PIC_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!xs->sigma_e[k]) return PIC_EINVAL;
+  for (int k = 0; k < 2; ++k)
+    if (!xs->sigma_i[k]) return PIC_EINVAL;
+  if (!(xs->exc_threshold_ev >= 0) || !(xs->ion_threshold_ev >= 0)) return PIC_EINVAL;
+  const uint32_t known = PIC_FLAG_NO_FIELD | PIC_FLAG_FIXED_E | PIC_FLAG_NO_COLL |
+                         PIC_FLAG_IMMOBILE_IONS | PIC_FLAG_RECORD | PIC_FLAG_THOMAS;
+  if (p->flags & ~known) return PIC_EINVAL;
+  return PIC_OK;
+}
+
+Layout make_layout(const pic_params* p, const pic_xsec* xs) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes > 0 ? bytes : 1);
+    return o;
+  };
+  const int nx = p->n_cells + 1;
+  L.ctl = take(sizeof(DevCtl));
+  for (int s = 0; s < 2; ++s) {
+    const int64_t cap = p->capacity[s];
+    L.max_tiles[s] = (cap + kTile - 1) / kTile + 1;
+    for (int b = 0; b < 2; ++b)
+      for (int q = 0; q < 4; ++q) L.part[s][b][q] = take((size_t)cap * sizeof(double));
+    L.codes[s] = take((size_t)cap);
+    L.tstat[s] = take((size_t)L.max_tiles[s] * 2 * sizeof(uint64_t));
+  }
+  for (int b = 0; b < 2; ++b) L.dep_e[b] = take((size_t)nx * 8);
+  for (int b = 0; b < 2; ++b) L.dep_i[b] = take((size_t)nx * 8);
+  L.rho = take((size_t)nx * 8);
+  L.phi = take((size_t)nx * 8);
+  L.E = take((size_t)nx * 8);
+  L.cum[0] = take((size_t)3 * xs->n * 8);
+  L.cum[1] = take((size_t)2 * xs->n * 8);
+  L.th_cp = take((size_t)nx * 8);
+  L.th_m = take((size_t)nx * 8);
+  L.acc_ne = take((size_t)nx * 8);
+  L.acc_ni = take((size_t)nx * 8);
+  L.acc_w = take((size_t)nx * 8);
+  L.acc_ew = take((size_t)nx * 8);
+  L.eepf = take((size_t)p->eepf_bins * 8);
+  int64_t capmax = p->capacity[0] > p->capacity[1] ? p->capacity[0] : p->capacity[1];
+  int sb = (int)((capmax + 16383) / 16384);
+  if (sb < 1) sb = 1;
+  if (sb > 512) sb = 512;
+  L.sort_blocks = sb;
+  L.sort_cnt = take((size_t)sb * (size_t)(nx - 1) * sizeof(uint32_t));
+  L.total = off;
+  return L;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EHIP; }
+
+#define HIP_TRY(expr)                        \
+  do {                                       \
+    hipError_t _e = (expr);                  \
+    if (_e != hipSuccess) return PIC_EHIP;   \
+  } while (0)
+
+int latched(pic_handle* h) {
+  uint32_t err = 0;
+  HIP_TRY(hipMemcpyAsync(&err, &h->ctl->err, sizeof(err), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (err & kErrLookback) return PIC_EHIP;
+  if (err & kErrUnstable) return PIC_EUNSTABLE;
+  if (err & kErrCapacity) return PIC_ECAPACITY;
+  if (err & kErrTable) return PIC_ETABLE;
+  return PIC_OK;
+}
+
+int field_mode(const pic_handle* h) {
+  const uint32_t f = h->p.flags;
+  if (f & PIC_FLAG_NO_FIELD) return FIELD_ZERO;
+  if (f & PIC_FLAG_FIXED_E) return FIELD_FIXED;
+  if (f & PIC_FLAG_THOMAS) return FIELD_THOMAS;
+  return FIELD_EXACT;
+}
+
+PartArgs particle_args(pic_handle* h, int sp, int parity) {
+  PartArgs a{};
+  const int in = h->cur[sp], out = 1 - h->cur[sp];
+  a.xin = h->part[sp][in][0];
+  a.vxin = h->part[sp][in][1];
+  a.vyin = h->part[sp][in][2];
+  a.vzin = h->part[sp][in][3];
+  a.xout = h->part[sp][out][0];
+  a.vxout = h->part[sp][out][1];
+  a.vyout = h->part[sp][out][2];
+  a.vzout = h->part[sp][out][3];
+  const int other = 1 - sp;
+  // electrons append ions to the current ion buffer; ions append secondary
+  // electrons to the electron buffer the electron kernel has just written
+  const int ob = h->cur[other];
+  a.bx = h->part[other][ob][0];
+  a.bvx = h->part[other][ob][1];
+  a.bvy = h->part[other][ob][2];
+  a.bvz = h->part[other][ob][3];
+  a.E = h->E;
+  if (sp == 0) {
+    a.dep_own = reinterpret_cast<unsigned long long*>(h->dep_e[parity ^ 1]);
+    a.dep_other = reinterpret_cast<unsigned long long*>(h->dep_i[h->cur_hi]);
+  } else {
+    a.dep_own = reinterpret_cast<unsigned long long*>(h->dep_i[1 - h->cur_hi]);
+    a.dep_other = reinterpret_cast<unsigned long long*>(h->dep_e[parity ^ 1]);
+  }
+  a.cum = h->cum[sp];
+  a.ctl = h->ctl;
+  a.tstat = h->tstat[sp];
+  a.codes = h->codes[sp];
+  a.acc_ew = h->acc_ew;
+  a.eepf = h->eepf;
+  a.cap = h->p.capacity[sp];
+  a.bcap = h->p.capacity[other];
+  a.max_tiles = h->max_tiles[sp];
+  a.inv_dx = h->inv_dx;
+  a.L = h->L;
+  a.acc = h->acc[sp];
+  a.dts = h->dts[sp];
+  a.p_wall = sp == 0 ? h->p.reflection : h->p.gamma_see;
+  a.pcoll = h->pcoll[sp];
+  a.numax = h->numax[sp];
+  a.inv_dv = h->inv_dv[sp];
+  a.mr = h->mr_e;
+  a.mm = h->mm_e;
+  a.ek = h->ek_e;
+  a.ve = h->ve_e;
+  a.exc_thr = h->exc_thr;
+  a.ion_thr = h->ion_thr;
+  a.sig_g = h->sig_g;
+  a.sig_se = h->sig_se;
+  a.half = 0.5 * h->L;
+  a.eepf_hw = h->p.eepf_halfwidth_m;
+  a.inv_de = h->inv_de;
+  a.nx = h->nx;
+  a.ntab = h->ntab;
+  a.nbins = h->p.eepf_bins;
+  a.parity = parity;
+  a.step = (uint32_t)h->step;
+  a.seed = h->p.seed;
+  a.run = h->p.run;
+  a.epoch = ++h->epoch;
+  a.no_coll = (h->p.flags & PIC_FLAG_NO_COLL) ? 1 : 0;
+  a.record = (h->p.flags & PIC_FLAG_RECORD) ? 1 : 0;
+  return a;
+}
+
+int sort_species(pic_handle* h, int sp) {
+  SortArgs a{};
+  const int in = h->cur[sp], out = 1 - h->cur[sp];
+  for (int q = 0; q < 4; ++q) {
+    a.src[q] = h->part[sp][in][q];
+    a.dst[q] = h->part[sp][out][q];
+  }
+  a.count = sp == 0 ? &h->ctl->n_e[h->step & 1] : &h->ctl->n_i[h->step & 1];
+  a.cap = h->p.capacity[sp];
+  a.cnt = h->sort_cnt;
+  a.inv_dx = h->inv_dx;
+  a.nx = h->nx;
+  a.nblocks = h->sort_blocks;
+  HIP_TRY(launch_sort(a, h->stream));
+  h->cur[sp] = out;
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pic_strerror(int s) {
+  switch (s) {
+    case PIC_OK: return "ok";
+    case PIC_EINVAL: return "invalid argument or parameter set";
+    case PIC_EHIP: return "HIP runtime error (no GPU, or a launch failed)";
+    case PIC_ECAPACITY: return "a species outgrew its capacity";
+    case PIC_EUNSTABLE: return "non-finite position, velocity or field";
+    case PIC_ETABLE: return "collision candidate beyond its cross-section table";
+    case PIC_ESTATE: return "call not valid in the current state";
+    default: return "unknown status";
+  }
+}
+
+int pic_workspace_bytes(const pic_params* p, const pic_xsec* xs, uint64_t* bytes) {
+  if (!bytes) return PIC_EINVAL;
+  const int v = validate(p, xs);
+  if (v) return v;
+  *bytes = make_layout(p, xs).total;
+  return PIC_OK;
+}
+
+int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t workspace_bytes,
+             void* stream, pic_handle** out) {
+  if (!out) return PIC_EINVAL;
+  *out = nullptr;
+  int v = validate(p, xs);
+  if (v) return v;
+  const Layout L = make_layout(p, xs);
+  if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace % kAlign) != 0)
+    return PIC_EINVAL;
+  pic_handle* h = new (std::nothrow) pic_handle();
+  if (!h) return PIC_EINVAL;
+  h->p = *p;
+  h->stream = (hipStream_t)stream;
+  if (hipGetDevice(&h->device) != hipSuccess ||
+      hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device) !=
+          hipSuccess) {
+    delete h;
+    return PIC_EHIP;
+  }
+
+  // ---- derived constants (Sec. 2): the operation order is part of the
+  // method's definition, so every side computes them the same way
+  h->nx = p->n_cells + 1;
+  h->L = p->gap_m;
+  h->dx = p->gap_m / (double)p->n_cells;
+  h->inv_dx = 1.0 / h->dx;
+  h->dt = 1.0 / (p->rf_freq_hz * (double)p->steps_per_cycle);
+  h->ng = p->pressure_pa / (kKb * p->gas_temp_k);
+  h->mass[0] = kMe;
+  h->mass[1] = 39.948 * kAmu;
+  h->dts[0] = h->dt;
+  h->dts[1] = (double)p->ion_subcycle * h->dt;
+  h->acc[0] = (-kQe / h->mass[0]) * h->dts[0];
+  h->acc[1] = (kQe / h->mass[1]) * h->dts[1];
+  h->nfac32 = p->weight / (p->area_m2 * h->dx) * kInvTwo32;
+  h->qfac32 = kQe * h->nfac32;
+  h->kpois = h->dx * h->dx * h->qfac32 / kEps0;
+  h->inv_dv[0] = 1.0 / xs->dv_e;
+  h->inv_dv[1] = 1.0 / xs->dv_i;
+  h->ntab = xs->n;
+  h->exc_thr = xs->exc_threshold_ev;
+  h->ion_thr = xs->ion_threshold_ev;
+  h->ek_e = 0.5 * kMe / kQe;
+  h->ve_e = 2.0 * kQe / kMe;
+  h->mr_e = kMe / (kMe + h->mass[1]);
+  h->mm_e = h->mass[1] / (kMe + h->mass[1]);
+  h->sig_g = std::sqrt(kKb * p->gas_temp_k / h->mass[1]);
+  h->sig_se = std::sqrt(p->see_temp_ev * kQe / kMe);
+  h->eepf_de = p->eepf_emax_ev / (double)p->eepf_bins;
+  h->inv_de = (double)p->eepf_bins / p->eepf_emax_ev;
+
+  // cumulative collision frequencies nu_k(v) = n_g sigma_k(v) v on the table
+  // speeds, and nu_max over the table (Sec. 3.5)
+  std::vector<double> cum[2];
+  const double* sig[2][3] = {{xs->sigma_e[0], xs->sigma_e[1], xs->sigma_e[2]},
+                             {xs->sigma_i[0], xs->sigma_i[1], nullptr}};
+  const int nproc[2] = {3, 2};
+  const double dv[2] = {xs->dv_e, xs->dv_i};
+  for (int s = 0; s < 2; ++s) {
+    cum[s].assign((size_t)nproc[s] * xs->n, 0.0);
+    h->numax[s] = 0.0;
+    for (int i = 0; i < xs->n; ++i) {
+      const double vel = (double)i * dv[s];
+      double run = 0.0;
+      for (int k = 0; k < nproc[s]; ++k) {
+        const double nu = h->ng * sig[s][k][i] * vel;
+        run = (k == 0) ? nu : run + nu;
+        cum[s][(size_t)k * xs->n + i] = run;
+      }
+      if (run > h->numax[s]) h->numax[s] = run;
+    }
+    h->pcoll[s] = 1.0 - std::exp(-h->numax[s] * h->dts[s]);
+  }
+  h->vtab.resize(p->steps_per_cycle);
+  for (int m = 0; m < p->steps_per_cycle; ++m)
+    h->vtab[m] = p->rf_voltage_v * std::cos(kTwoPi * (double)m / (double)p->steps_per_cycle);
+  // Thomas recurrence coefficients of the constant [1, -2, 1] matrix
+  std::vector<double> th_cp(h->nx, 0.0), th_m(h->nx, 0.0);
+  {
+    const int n = h->nx - 2;
+    th_cp[0] = 1.0 / -2.0;
+    th_m[0] = -2.0;
+    for (int i = 1; i < n; ++i) {
+      const double m = -2.0 - 1.0 * th_cp[i - 1];
+      th_m[i] = m;
+      th_cp[i] = 1.0 / m;
+    }
+  }
+
+  // ---- workspace
+  char* w = static_cast<char*>(workspace);
+  h->ctl = reinterpret_cast<DevCtl*>(w + L.ctl);
+  for (int s = 0; s < 2; ++s) {
+    for (int b = 0; b < 2; ++b)
+      for (int q = 0; q < 4; ++q) h->part[s][b][q] = reinterpret_cast<double*>(w + L.part[s][b][q]);
+    h->codes[s] = reinterpret_cast<uint8_t*>(w + L.codes[s]);
+    h->tstat[s] = reinterpret_cast<uint64_t*>(w + L.tstat[s]);
+    h->max_tiles[s] = L.max_tiles[s];
+    h->cum[s] = reinterpret_cast<double*>(w + L.cum[s]);
+  }
+  for (int b = 0; b < 2; ++b) {
+    h->dep_e[b] = reinterpret_cast<int64_t*>(w + L.dep_e[b]);
+    h->dep_i[b] = reinterpret_cast<int64_t*>(w + L.dep_i[b]);
+  }
+  h->rho = reinterpret_cast<double*>(w + L.rho);
+  h->phi = reinterpret_cast<double*>(w + L.phi);
+  h->E = reinterpret_cast<double*>(w + L.E);
+  h->th_cp = reinterpret_cast<double*>(w + L.th_cp);
+  h->th_m = reinterpret_cast<double*>(w + L.th_m);
+  h->acc_ne = reinterpret_cast<double*>(w + L.acc_ne);
+  h->acc_ni = reinterpret_cast<double*>(w + L.acc_ni);
+  h->acc_w = reinterpret_cast<double*>(w + L.acc_w);
+  h->acc_ew = reinterpret_cast<double*>(w + L.acc_ew);
+  h->eepf = reinterpret_cast<unsigned long long*>(w + L.eepf);
+  h->sort_cnt = reinterpret_cast<uint32_t*>(w + L.sort_cnt);
+  h->sort_blocks = L.sort_blocks;
+  h->step = 0;
+  h->cur[0] = h->cur[1] = 0;
+  h->cur_hi = 0;
+  h->measuring = 0;
+  h->epoch = 0;
+
+  int st = PIC_OK;
+  if (hipMemsetAsync(workspace, 0, L.total, h->stream) != hipSuccess ||
+      hipMemcpyAsync(h->cum[0], cum[0].data(), cum[0].size() * 8, hipMemcpyHostToDevice,
+                     h->stream) != hipSuccess ||
+      hipMemcpyAsync(h->cum[1], cum[1].data(), cum[1].size() * 8, hipMemcpyHostToDevice,
+                     h->stream) != hipSuccess ||
+      hipMemcpyAsync(h->th_cp, th_cp.data(), th_cp.size() * 8, hipMemcpyHostToDevice,
+                     h->stream) != hipSuccess ||
+      hipMemcpyAsync(h->th_m, th_m.data(), th_m.size() * 8, hipMemcpyHostToDevice, h->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    st = PIC_EHIP;
+  if (st) {
+    delete h;
+    return st;
+  }
+  for (int m = 0; m < 2; ++m) {
+    h->lds[m] = particle_lds_bytes(h->nx, m == 1, p->eepf_bins);
+    for (int s = 0; s < 2; ++s) {
+      const int bpc = particle_blocks_per_cu(s, m == 1 && s == 0, h->lds[m]);
+      int64_t g = (int64_t)bpc * h->num_cu;
+      if (g > h->max_tiles[s]) g = h->max_tiles[s];
+      if (g < 1) g = 1;
+      h->grid[s][m] = (int)g;
+    }
+  }
+  h->d.n_x = h->nx;
+  h->d.n_tiles_max = (int32_t)(L.max_tiles[0] > L.max_tiles[1] ? L.max_tiles[0] : L.max_tiles[1]);
+  h->d.dx = h->dx;
+  h->d.dt = h->dt;
+  h->d.gas_density = h->ng;
+  for (int s = 0; s < 2; ++s) {
+    h->d.nu_max[s] = h->numax[s];
+    h->d.p_coll[s] = h->pcoll[s];
+  }
+  *out = h;
+  return PIC_OK;
+}
+
+int pic_get_derived(const pic_handle* h, pic_derived* d) {
+  if (!h || !d) return PIC_EINVAL;
+  *d = h->d;
+  return PIC_OK;
+}
+
+int pic_set_state(pic_handle* h, int species, const double* x, const double* vx, const double* vy,
+                  const double* vz, int64_t n, int64_t step) {
+  if (!h || species < 0 || species > 1 || n < 0 || step < 0) return PIC_EINVAL;
+  if (n > 0 && (!x || !vx || !vy || !vz)) return PIC_EINVAL;
+  if (n > h->p.capacity[species]) return PIC_ECAPACITY;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const int old_par = (int)(h->step & 1), par = (int)(step & 1);
+  if (old_par != par) {
+    // keep the other species' count and (for electrons) deposit on the new parity
+    if (species == 1) {
+      HIP_TRY(hipMemcpyAsync(&h->ctl->n_e[par], &h->ctl->n_e[old_par], 8,
+                             hipMemcpyDeviceToDevice, h->stream));
+      HIP_TRY(hipMemcpyAsync(h->dep_e[par], h->dep_e[old_par], (size_t)h->nx * 8,
+                             hipMemcpyDeviceToDevice, h->stream));
+    } else {
+      HIP_TRY(hipMemcpyAsync(&h->ctl->n_i[par], &h->ctl->n_i[old_par], 8,
+                             hipMemcpyDeviceToDevice, h->stream));
+    }
+  }
+  h->step = step;
+  double* const* dst = h->part[species][h->cur[species]];
+  const double* src[4] = {x, vx, vy, vz};
+  for (int q = 0; q < 4; ++q)
+    if (n > 0)
+      HIP_TRY(hipMemcpyAsync(dst[q], src[q], (size_t)n * 8, hipMemcpyDefault, h->stream));
+  int64_t nn = n;
+  int64_t* cnt = species == 0 ? &h->ctl->n_e[par] : &h->ctl->n_i[par];
+  HIP_TRY(hipMemcpyAsync(cnt, &nn, 8, hipMemcpyHostToDevice, h->stream));
+  int64_t* dep = species == 0 ? h->dep_e[par] : h->dep_i[h->cur_hi];
+  HIP_TRY(hipMemsetAsync(dep, 0, (size_t)h->nx * 8, h->stream));
+  HIP_TRY(launch_deposit(dst[0], cnt, h->inv_dx, h->nx, reinterpret_cast<unsigned long long*>(dep),
+                         h->stream));
+  HIP_TRY(hipMemsetAsync(h->ctl->counters, 0, sizeof(h->ctl->counters), h->stream));
+  HIP_TRY(hipMemsetAsync(&h->ctl->err, 0, sizeof(uint32_t), h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return PIC_OK;
+}
+
+int pic_get_state(pic_handle* h, int species, double* x, double* vx, double* vy, double* vz,
+                  int64_t cap, int64_t* n, int64_t* step) {
+  if (!h || species < 0 || species > 1 || !n) return PIC_EINVAL;
+  const int err = latched(h);
+  const int par = (int)(h->step & 1);
+  int64_t cnt = 0;
+  HIP_TRY(hipMemcpyAsync(&cnt, species == 0 ? &h->ctl->n_e[par] : &h->ctl->n_i[par], 8,
+                         hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  *n = cnt;
+  if (step) *step = h->step;
+  if (err) return err;
+  if (cnt > cap) return PIC_ECAPACITY;
+  double* out[4] = {x, vx, vy, vz};
+  for (int q = 0; q < 4; ++q) {
+    if (cnt > 0 && !out[q]) return PIC_EINVAL;
+    if (cnt > 0)
+      HIP_TRY(hipMemcpyAsync(out[q], h->part[species][h->cur[species]][q], (size_t)cnt * 8,
+                             hipMemcpyDefault, h->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return PIC_OK;
+}
+
+int pic_step(pic_handle* h, int64_t n_steps) {
+  if (!h || n_steps < 0) return PIC_EINVAL;
+  if ((h->p.flags & PIC_FLAG_FIXED_E) && !h->field_fixed_set) return PIC_ESTATE;
+  const pic_params& p = h->p;
+  const int mode = field_mode(h);
+  for (int64_t it = 0; it < n_steps; ++it) {
+    const int par = (int)(h->step & 1);
+    const bool ion_step =
+        !(p.flags & PIC_FLAG_IMMOBILE_IONS) && (h->step % p.ion_subcycle == 0);
+    FieldArgs f{};
+    f.dep_e = h->dep_e[par];
+    f.dep_i = h->dep_i[h->cur_hi];
+    f.zero_a = h->dep_e[par ^ 1];
+    f.zero_b = ion_step ? h->dep_i[1 - h->cur_hi] : nullptr;
+    f.rho = h->rho;
+    f.phi = h->phi;
+    f.E = h->E;
+    f.th_cp = h->th_cp;
+    f.th_m = h->th_m;
+    f.acc_ne = h->acc_ne;
+    f.acc_ni = h->acc_ni;
+    f.acc_w = h->acc_w;
+    f.ctl = h->ctl;
+    f.V = h->vtab[(size_t)(h->step % p.steps_per_cycle)];
+    f.dx = h->dx;
+    f.qfac32 = h->qfac32;
+    f.nfac32 = h->nfac32;
+    f.kpois = h->kpois;
+    f.nx = h->nx;
+    f.mode = mode;
+    f.measuring = h->measuring;
+    f.parity = par;
+    HIP_TRY(launch_field(f, h->stream));
+
+    const int m = h->measuring ? 1 : 0;
+    PartArgs ae = particle_args(h, 0, par);
+    HIP_TRY(launch_particles(0, m == 1, ae, h->grid[0][m], h->lds[m], h->stream));
+    h->cur[0] ^= 1;
+    if (ion_step) {
+      PartArgs ai = particle_args(h, 1, par);
+      HIP_TRY(launch_particles(1, false, ai, h->grid[1][0], h->lds[0], h->stream));
+      h->cur[1] ^= 1;
+      h->cur_hi ^= 1;
+    }
+    h->step += 1;
+    if (p.sort_interval > 0 && h->step % p.sort_interval == 0) {
+      int s = sort_species(h, 0);
+      if (s) return s;
+      s = sort_species(h, 1);
+      if (s) return s;
+    }
+  }
+  return PIC_OK;
+}
+
+int pic_sync(pic_handle* h) {
+  if (!h) return PIC_EINVAL;
+  return latched(h);
+}
+
+int pic_set_field(pic_handle* h, const double* E) {
+  if (!h || !E) return PIC_EINVAL;
+  if (!(h->p.flags & PIC_FLAG_FIXED_E)) return PIC_ESTATE;
+  HIP_TRY(hipMemcpyAsync(h->E, E, (size_t)h->nx * 8, hipMemcpyDefault, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->field_fixed_set = 1;
+  return PIC_OK;
+}
+
+int pic_get_field(pic_handle* h, double* rho, double* phi, double* E, int64_t* deposit_e,
+                  int64_t* deposit_i) {
+  if (!h) return PIC_EINVAL;
+  const size_t b = (size_t)h->nx * 8;
+  const int par = (int)(h->step & 1);
+  if (rho) HIP_TRY(hipMemcpyAsync(rho, h->rho, b, hipMemcpyDefault, h->stream));
+  if (phi) HIP_TRY(hipMemcpyAsync(phi, h->phi, b, hipMemcpyDefault, h->stream));
+  if (E) HIP_TRY(hipMemcpyAsync(E, h->E, b, hipMemcpyDefault, h->stream));
+  if (deposit_e) HIP_TRY(hipMemcpyAsync(deposit_e, h->dep_e[par], b, hipMemcpyDefault, h->stream));
+  if (deposit_i)
+    HIP_TRY(hipMemcpyAsync(deposit_i, h->dep_i[h->cur_hi], b, hipMemcpyDefault, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return latched(h);
+}
+
+int pic_measure(pic_handle* h, int on) {
+  if (!h) return PIC_EINVAL;
+  h->measuring = on ? 1 : 0;
+  return PIC_OK;
+}
+
+int pic_moments(pic_handle* h, pic_moments_out* out, int reset) {
+  if (!h || !out) return PIC_EINVAL;
+  const int nx = h->nx, nb = h->p.eepf_bins;
+  std::vector<double> ne(nx), ni(nx), w(nx), ew(nx);
+  std::vector<unsigned long long> hist(nb);
+  int64_t msteps = 0;
+  HIP_TRY(hipMemcpyAsync(ne.data(), h->acc_ne, nx * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(ni.data(), h->acc_ni, nx * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(w.data(), h->acc_w, nx * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(ew.data(), h->acc_ew, nx * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(hist.data(), h->eepf, nb * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(&msteps, &h->ctl->msteps, 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int j = 0; j < nx; ++j) {
+    if (out->n_e) out->n_e[j] = msteps ? ne[j] / (double)msteps : 0.0;
+    if (out->n_i) out->n_i[j] = msteps ? ni[j] / (double)msteps : 0.0;
+    if (out->mean_energy_e) out->mean_energy_e[j] = w[j] > 0.0 ? ew[j] / w[j] : 0.0;
+  }
+  if (out->eepf) {
+    unsigned long long tot = 0;
+    for (int b = 0; b < nb; ++b) tot += hist[b];
+    for (int b = 0; b < nb; ++b) {
+      const double eb = ((double)b + 0.5) * h->eepf_de;
+      out->eepf[b] = tot ? (double)hist[b] / ((double)tot * std::sqrt(eb) * h->eepf_de) : 0.0;
+    }
+  }
+  out->steps_averaged = msteps;
+  if (reset) {
+    HIP_TRY(hipMemsetAsync(h->acc_ne, 0, nx * 8, h->stream));
+    HIP_TRY(hipMemsetAsync(h->acc_ni, 0, nx * 8, h->stream));
+    HIP_TRY(hipMemsetAsync(h->acc_w, 0, nx * 8, h->stream));
+    HIP_TRY(hipMemsetAsync(h->acc_ew, 0, nx * 8, h->stream));
+    HIP_TRY(hipMemsetAsync(h->eepf, 0, nb * 8, h->stream));
+    HIP_TRY(hipMemsetAsync(&h->ctl->msteps, 0, 8, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  }
+  return latched(h);
+}
+
+int pic_get_counters(pic_handle* h, int64_t* counters) {
+  if (!h || !counters) return PIC_EINVAL;
+  unsigned long long c[NCOUNTERS];
+  HIP_TRY(hipMemcpyAsync(c, h->ctl->counters, sizeof(c), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < NCOUNTERS; ++i) counters[i] = (int64_t)c[i];
+  return latched(h);
+}
+
+int pic_get_decisions(pic_handle* h, int species, uint8_t* codes, int64_t cap, int64_t* n) {
+  if (!h || species < 0 || species > 1 || !n) return PIC_EINVAL;
+  if (!(h->p.flags & PIC_FLAG_RECORD)) return PIC_ESTATE;
+  int64_t cnt = 0;
+  HIP_TRY(hipMemcpyAsync(&cnt, &h->ctl->ncodes[species], 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  *n = cnt;
+  if (cnt > cap) return PIC_ECAPACITY;
+  if (cnt > 0) {
+    if (!codes) return PIC_EINVAL;
+    HIP_TRY(hipMemcpyAsync(codes, h->codes[species], (size_t)cnt, hipMemcpyDefault, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  }
+  return latched(h);
+}
+
+void pic_free(pic_handle* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+int pic_selftest_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
+                        void* stream) {
+  if (n < 0 || !key || (n > 0 && (!ctr || !out))) return PIC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_selftest_philox(ctr, key[0], key[1], out, n, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return PIC_OK;
+}
+
+int pic_selftest_sqrt(const double* in, double* out, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!in || !out))) return PIC_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(launch_selftest_sqrt(in, out, n, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return PIC_OK;
+}
+
+}  // extern "C"

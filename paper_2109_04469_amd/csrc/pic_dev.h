@@ -1,0 +1,180 @@
+// Device-side definitions shared by the libpic kernels (gfx950, wave64).
+//
+// Arithmetic conventions (they make every decision of a step bitwise
+// reproducible on any execution order): FP64 IEEE round-to-nearest with no
+// contraction (-ffp-contract=off), correctly rounded division and sqrt, CIC
+// weights in 2^-32 fixed point with integer accumulation, and all random
+// draws from Philox4x32-10 keyed by (seed, run) with counter
+// (step, slot, 16*species + purpose, 0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+constexpr int kBlock = 256;          // threads per particle workgroup (4 waves)
+constexpr int kPPT = 4;              // particles per thread per tile
+constexpr int kTile = kBlock * kPPT;  // particles per tile
+constexpr int kWave = 64;
+
+constexpr double kTwoPi = 6.283185307179586;
+constexpr double kTwo32 = 4294967296.0;
+constexpr double kInvTwo32 = 2.3283064365386963e-10;
+constexpr int64_t kOne32 = 4294967296LL;
+
+// latched device error bits
+constexpr uint32_t kErrUnstable = 1u;
+constexpr uint32_t kErrCapacity = 2u;
+constexpr uint32_t kErrTable = 4u;
+constexpr uint32_t kErrLookback = 8u;  // a tile's prefix wait hit its bound
+
+// decision code bits (per pushed slot)
+constexpr uint8_t kCodePushed = 0x80;
+
+enum Counter {
+  C_STEPS = 0, C_E_PUSHED, C_I_PUSHED, C_E_ABSORBED, C_E_REFLECTED, C_I_ABSORBED,
+  C_SE_EMITTED, C_E_CAND, C_E_ELASTIC, C_E_EXC, C_E_ION, C_I_CAND, C_I_ISO, C_I_BACK,
+  C_REFLECT_LOST, C_RESERVED, NCOUNTERS
+};
+
+// Control block in device memory. Counts are double-buffered by step parity:
+// step n reads n_*[n & 1] and produces n_*[(n + 1) & 1].
+struct DevCtl {
+  int64_t n_e[2];
+  int64_t n_i[2];
+  int64_t e_out;      // outputs of this step's electron kernel
+  int64_t i_births;   // ions appended by this step's electron kernel
+  int64_t ncodes[2];  // slots with a decision code from the last step
+  int64_t msteps;     // measured steps
+  unsigned long long counters[NCOUNTERS];
+  uint32_t ticket[2];
+  uint32_t err;
+  uint32_t pad;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11).
+__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                   (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+  }
+  return c;
+}
+
+__device__ __forceinline__ uint4 draw(uint32_t step, uint32_t slot, uint32_t species,
+                                      uint32_t purpose, uint32_t seed, uint32_t run) {
+  return philox(make_uint4(step, slot, 16u * species + purpose, 0u), seed, run);
+}
+
+// u32 -> (r + 1/2) 2^-32, exact in FP64, strictly inside (0, 1)
+__device__ __forceinline__ double u01(uint32_t r) { return ((double)r + 0.5) * kInvTwo32; }
+
+__device__ __forceinline__ void box_muller(double u1, double u2, double& a, double& b) {
+  const double rad = sqrt(-2.0 * log(u1));
+  const double th = kTwoPi * u2;
+  double s, c;
+  sincos(th, &s, &c);
+  a = rad * c;
+  b = rad * s;
+}
+
+__device__ __forceinline__ void iso_dir(double ua, double ub, double& nx, double& ny,
+                                        double& nz) {
+  const double cth = 1.0 - 2.0 * ua;
+  const double sth = 2.0 * sqrt(ua * (1.0 - ua));
+  const double ph = kTwoPi * ub;
+  double s, c;
+  sincos(ph, &s, &c);
+  nx = cth;
+  ny = sth * c;
+  nz = sth * s;
+}
+
+// Cell index j in [0, nx-2], fraction f and fixed-point weight w1 of node
+// j+1 (node j receives 2^32 - w1).
+__device__ __forceinline__ void cell_of(double x, double inv_dx, int nx, int& j, double& f,
+                                        int64_t& w1) {
+  const double t = x * inv_dx;
+  int jj = (int)t;
+  if (jj > nx - 2) jj = nx - 2;
+  if (jj < 0) jj = 0;
+  j = jj;
+  f = t - (double)jj;
+  int64_t w = (int64_t)floor(f * kTwo32 + 0.5);
+  if (w < 0) w = 0;
+  if (w > kOne32) w = kOne32;
+  w1 = w;
+}
+
+__device__ __forceinline__ int cell_key(double x, double inv_dx, int nx) {
+  const double t = x * inv_dx;
+  int jj = (int)t;
+  if (jj > nx - 2) jj = nx - 2;
+  if (jj < 0) jj = 0;
+  return jj;
+}
+
+// Wave-uniform copies of values every lane holds alike. Loop bounds and
+// exits of loops that contain workgroup barriers must be visibly uniform to
+// the compiler; otherwise it may restructure the loop so that lanes take
+// different paths around the barrier.
+__device__ __forceinline__ int uniform32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ void latch_error(DevCtl* ctl, uint32_t bit) {
+  atomicOr(&ctl->err, bit);
+}
+
+// ---------------------------------------------------------------------------
+// agent-scope atomic helpers (the status words of the decoupled look-back)
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// wave-level inclusive scan (64 lanes)
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T u = __shfl_up(v, o, kWave);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+}  // namespace pic

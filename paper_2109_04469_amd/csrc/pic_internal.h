@@ -1,0 +1,177 @@
+// Internal declarations of libpic: kernel argument blocks (shared by the
+// device code and the host launchers) and the host-side handle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/pic.h"
+#include "pic_dev.h"
+
+namespace pic {
+
+constexpr double kQe = 1.602176634e-19;     // CODATA 2018
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kKb = 1.380649e-23;
+
+enum FieldMode { FIELD_EXACT = 0, FIELD_ZERO = 1, FIELD_FIXED = 2, FIELD_THOMAS = 3 };
+
+struct FieldArgs {
+  const int64_t* dep_e;
+  const int64_t* dep_i;
+  int64_t* zero_a;  // deposit buffers cleared for this step's particle kernels
+  int64_t* zero_b;
+  double* rho;
+  double* phi;
+  double* E;
+  const double* th_cp;  // Thomas recurrence coefficients (FIELD_THOMAS)
+  const double* th_m;
+  double* acc_ne;
+  double* acc_ni;
+  double* acc_w;
+  DevCtl* ctl;
+  double V;
+  double dx;
+  double qfac32;  // e W / (A dx) 2^-32
+  double nfac32;  // W / (A dx) 2^-32
+  double kpois;   // dx^2 qfac32 / eps0
+  int nx;
+  int mode;
+  int measuring;
+  int parity;
+};
+
+struct PartArgs {
+  const double* xin;
+  const double* vxin;
+  const double* vyin;
+  const double* vzin;
+  double* xout;
+  double* vxout;
+  double* vyout;
+  double* vzout;
+  // births of the other species are appended here
+  double* bx;
+  double* bvx;
+  double* bvy;
+  double* bvz;
+  const double* E;
+  unsigned long long* dep_own;    // deposit of this kernel's outputs
+  unsigned long long* dep_other;  // deposit of the other species' births
+  const double* cum;              // cumulative nu tables, nproc x ntab
+  DevCtl* ctl;
+  uint64_t* tstat;  // look-back status words, 2 per tile
+  uint8_t* codes;
+  double* acc_ew;                // CIC-weighted energy (electrons, measuring)
+  unsigned long long* eepf;     // EEPF histogram (electrons, measuring)
+  int64_t cap;                  // capacity of the output arrays
+  int64_t bcap;                 // capacity of the birth target arrays
+  int64_t max_tiles;
+  double inv_dx;
+  double L;
+  double acc;      // (q/m) dt_s
+  double dts;
+  double p_wall;   // R (electrons) or gamma (ions)
+  double pcoll;
+  double numax;
+  double inv_dv;
+  double mr;       // m/(m+M) (electron elastic)
+  double mm;       // M/(m+M)
+  double ek;       // 1/2 m / e  (J -> eV factor times m/2)
+  double ve;       // 2 e / m
+  double exc_thr;
+  double ion_thr;
+  double sig_g;    // sqrt(k T_g / M)
+  double sig_se;   // sqrt(e T_se / m_e)
+  double half;     // L/2
+  double eepf_hw;
+  double inv_de;
+  int nx;
+  int ntab;
+  int nbins;
+  int parity;
+  uint32_t step;
+  uint32_t seed;
+  uint32_t run;
+  uint32_t epoch;
+  int no_coll;
+  int record;
+};
+
+struct SortArgs {
+  const double* src[4];
+  double* dst[4];
+  const int64_t* count;  // device count of the species
+  int64_t cap;           // capacity of src/dst
+  uint32_t* cnt;         // [nkeys][nblocks]
+  double inv_dx;
+  int nx;
+  int nblocks;
+};
+
+// host launchers
+hipError_t launch_field(const FieldArgs& a, hipStream_t s);
+hipError_t launch_particles(int species, bool measure, const PartArgs& a, int grid, size_t lds,
+                            hipStream_t s);
+size_t particle_lds_bytes(int nx, bool measure, int nbins);
+int particle_blocks_per_cu(int species, bool measure, size_t lds);
+hipError_t launch_sort(const SortArgs& a, hipStream_t s);
+hipError_t launch_deposit(const double* x, const int64_t* count, double inv_dx, int nx,
+                          unsigned long long* dep, hipStream_t s);
+hipError_t launch_selftest_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
+                                  int64_t n, hipStream_t s);
+hipError_t launch_selftest_sqrt(const double* in, double* out, int64_t n, hipStream_t s);
+
+}  // namespace pic
+
+struct pic_handle {
+  pic_params p;
+  pic_derived d;
+  hipStream_t stream;
+  int device;
+  int num_cu;
+  // derived constants
+  int nx;
+  double L, dx, inv_dx, dt, ng;
+  double dts[2], acc[2], mass[2];
+  double nfac32, qfac32, kpois;
+  double inv_dv[2], numax[2], pcoll[2];
+  double ek_e, ve_e, mr_e, mm_e, sig_g, sig_se, inv_de, eepf_de;
+  double exc_thr, ion_thr;
+  int ntab;
+  std::vector<double> vtab;
+  // device memory (carved from the caller's workspace)
+  pic::DevCtl* ctl;
+  double* part[2][2][4];  // [species][buffer][x, vx, vy, vz]
+  uint8_t* codes[2];
+  uint64_t* tstat[2];
+  int64_t max_tiles[2];
+  int64_t* dep_e[2];
+  int64_t* dep_i[2];
+  double* rho;
+  double* phi;
+  double* E;
+  double* cum[2];
+  double* th_cp;
+  double* th_m;
+  double* acc_ne;
+  double* acc_ni;
+  double* acc_w;
+  double* acc_ew;
+  unsigned long long* eepf;
+  uint32_t* sort_cnt;
+  int sort_blocks;
+  // host-side schedule state
+  int64_t step;
+  int cur[2];
+  int cur_hi;
+  int measuring;
+  int field_fixed_set;
+  uint32_t epoch;
+  int grid[2][2];     // [species][measure]
+  size_t lds[2];      // [measure]
+};

@@ -1,0 +1,201 @@
+"""Python handle on one simulated discharge. PyTorch provides the device
+workspace and the stream; every step of the method runs in libpic's HIP
+kernels, reached through the C ABI."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import capi
+from .capi import PicDerived, PicMomentsOut, PicParams, PicXsec, check
+
+_PARAM_FIELDS = [f for f, _ in PicParams._fields_]
+
+
+def make_params(params: dict) -> PicParams:
+    p = PicParams()
+    for name in _PARAM_FIELDS:
+        v = params[name]
+        if name == "capacity":
+            p.capacity[0], p.capacity[1] = int(v[0]), int(v[1])
+        else:
+            setattr(p, name, v)
+    return p
+
+
+def make_xsec(xs):
+    x = PicXsec()
+    x.n = xs.n
+    x.dv_e = xs.dv_e
+    x.dv_i = xs.dv_i
+    keep = []
+    for k, s in enumerate(xs.sigma_e):
+        a = np.ascontiguousarray(s, dtype=np.float64)
+        keep.append(a)
+        x.sigma_e[k] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for k, s in enumerate(xs.sigma_i):
+        a = np.ascontiguousarray(s, dtype=np.float64)
+        keep.append(a)
+        x.sigma_i[k] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    x.exc_threshold_ev = xs.exc_threshold_ev
+    x.ion_threshold_ev = xs.ion_threshold_ev
+    return x, keep
+
+
+def _ptr(a):
+    """Device or host address of a contiguous torch tensor / numpy array."""
+    if isinstance(a, torch.Tensor):
+        assert a.is_contiguous()
+        return ctypes.c_void_p(a.data_ptr())
+    assert a.flags["C_CONTIGUOUS"]
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Discharge:
+    """One RF discharge on one GPU (libpic handle + its torch workspace)."""
+
+    def __init__(self, params: dict, xs, device="cuda:0"):
+        self.L = capi.load()
+        self.device = torch.device(device)
+        self.params = dict(params)
+        self._p = make_params(params)
+        self._x, self._keep = make_xsec(xs)
+        nbytes = ctypes.c_uint64()
+        check(self.L.pic_workspace_bytes(ctypes.byref(self._p), ctypes.byref(self._x), ctypes.byref(nbytes)),
+              "pic_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(self.L.pic_init(ctypes.byref(self._p), ctypes.byref(self._x), ctypes.c_void_p(base + off),
+                              nbytes.value, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+              "pic_init")
+        self.h = h
+        self.nx = int(params["n_cells"]) + 1
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pic_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- state -----------------------------------------------------------
+    def set_state(self, species, x, vx, vy, vz, step=0):
+        arrs = []
+        for a in (x, vx, vy, vz):
+            if isinstance(a, torch.Tensor):
+                a = a.to(dtype=torch.float64).contiguous()
+            else:
+                a = np.ascontiguousarray(a, dtype=np.float64)
+            arrs.append(a)
+        n = int(arrs[0].shape[0])
+        check(self.L.pic_set_state(self.h, species, *[_ptr(a) for a in arrs], n, int(step)), "pic_set_state")
+
+    def count(self, species):
+        n = ctypes.c_int64()
+        st = ctypes.c_int64()
+        s = self.L.pic_get_state(self.h, species, None, None, None, None, 0, ctypes.byref(n), ctypes.byref(st))
+        if s not in (capi.PIC_OK, capi.PIC_ECAPACITY):
+            check(s, "pic_get_state")
+        return int(n.value)
+
+    def get_state(self, species, to_numpy=True):
+        n = self.count(species)
+        out = [torch.empty(max(n, 1), dtype=torch.float64, device=self.device) for _ in range(4)]
+        cnt = ctypes.c_int64()
+        st = ctypes.c_int64()
+        check(self.L.pic_get_state(self.h, species, *[_ptr(t) for t in out], n, ctypes.byref(cnt),
+                                   ctypes.byref(st)), "pic_get_state")
+        out = [t[:n] for t in out]
+        if to_numpy:
+            return tuple(t.cpu().numpy() for t in out)
+        return tuple(out)
+
+    @property
+    def step_index(self):
+        n = ctypes.c_int64()
+        st = ctypes.c_int64()
+        self.L.pic_get_state(self.h, 0, None, None, None, None, 0, ctypes.byref(n), ctypes.byref(st))
+        return int(st.value)
+
+    # ---- stepping ----------------------------------------------------------
+    def step(self, n=1):
+        check(self.L.pic_step(self.h, int(n)), "pic_step")
+
+    def sync(self):
+        return self.L.pic_sync(self.h)
+
+    def set_field(self, E):
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        assert E.size == self.nx
+        check(self.L.pic_set_field(self.h, _ptr(E)), "pic_set_field")
+
+    def get_field(self):
+        nx = self.nx
+        rho, phi, E = np.zeros(nx), np.zeros(nx), np.zeros(nx)
+        de, di = np.zeros(nx, np.int64), np.zeros(nx, np.int64)
+        check(self.L.pic_get_field(self.h, _ptr(rho), _ptr(phi), _ptr(E), _ptr(de), _ptr(di)), "pic_get_field")
+        return dict(rho=rho, phi=phi, E=E, dep_e=de, dep_i=di)
+
+    # ---- diagnostics -------------------------------------------------------
+    def measure(self, on=True):
+        check(self.L.pic_measure(self.h, 1 if on else 0), "pic_measure")
+
+    def moments(self, reset=False):
+        nx = self.nx
+        ne, ni, em = np.zeros(nx), np.zeros(nx), np.zeros(nx)
+        ep = np.zeros(int(self.params["eepf_bins"]))
+        out = PicMomentsOut()
+        dp = ctypes.POINTER(ctypes.c_double)
+        out.n_e = ne.ctypes.data_as(dp)
+        out.n_i = ni.ctypes.data_as(dp)
+        out.mean_energy_e = em.ctypes.data_as(dp)
+        out.eepf = ep.ctypes.data_as(dp)
+        check(self.L.pic_moments(self.h, ctypes.byref(out), 1 if reset else 0), "pic_moments")
+        return dict(n_e=ne, n_i=ni, mean_energy_e=em, eepf=ep, steps=int(out.steps_averaged))
+
+    def counters(self):
+        c = np.zeros(capi.NCOUNTERS, np.int64)
+        check(self.L.pic_get_counters(self.h, _ptr(c)), "pic_get_counters")
+        return c
+
+    def decisions(self, species):
+        cap = max(1, int(self.params["capacity"][species]))
+        buf = np.zeros(cap, np.uint8)
+        n = ctypes.c_int64()
+        check(self.L.pic_get_decisions(self.h, species, _ptr(buf), cap, ctypes.byref(n)), "pic_get_decisions")
+        return buf[: n.value].copy()
+
+    def derived(self):
+        d = PicDerived()
+        check(self.L.pic_get_derived(self.h, ctypes.byref(d)), "pic_get_derived")
+        return dict(n_x=d.n_x, n_tiles_max=d.n_tiles_max, dx=d.dx, dt=d.dt, gas_density=d.gas_density,
+                    nu_max_e=d.nu_max[0], nu_max_i=d.nu_max[1], p_coll_e=d.p_coll[0], p_coll_i=d.p_coll[1])
+
+
+def selftest_philox(ctr: np.ndarray, key, device="cuda:0"):
+    L = capi.load()
+    c = torch.as_tensor(np.ascontiguousarray(ctr, dtype=np.uint32).view(np.int32)).to(device)
+    out = torch.empty_like(c)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    s = torch.cuda.current_stream(torch.device(device))
+    n = c.numel() // 4
+    check(L.pic_selftest_philox(_ptr(c), _ptr(k), _ptr(out), n, ctypes.c_void_p(s.cuda_stream)), "selftest_philox")
+    return out.cpu().numpy().view(np.uint32).reshape(-1, 4)
+
+
+def selftest_sqrt(x: np.ndarray, device="cuda:0"):
+    L = capi.load()
+    t = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).to(device)
+    out = torch.empty_like(t)
+    s = torch.cuda.current_stream(torch.device(device))
+    check(L.pic_selftest_sqrt(_ptr(t), _ptr(out), t.numel(), ctypes.c_void_p(s.cuda_stream)), "selftest_sqrt")
+    return out.cpu().numpy()

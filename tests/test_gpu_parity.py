@@ -1,0 +1,239 @@
+"""GPU (libpic through the C ABI) against the CPU oracle.
+
+Single steps from a shared state must agree exactly in every decision
+(absorption, reflection, emission, collision process), in particle counts,
+slot order and integer deposits, and within 1e-12 relative in positions and
+velocities (only the scattering transcendentals may differ by ulps).
+"""
+import numpy as np
+import pytest
+
+from gpu_common import assert_state_close, assert_state_equal, need_gpu, pair
+from helpers import FIXED_E, NO_COLL, RECORD, THOMAS, ME, MAR, QE, params
+from pic_inputs import state, workloads, xsec
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _vth(T_ev, m):
+    return np.sqrt(T_ev * QE / m)
+
+
+def test_philox_matches_oracle():
+    import oracle
+    from paper_2109_04469_amd import selftest_philox
+
+    rng = np.random.default_rng(1)
+    n = 4096
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    key = np.array([123456789, 987654321], dtype=np.uint32)
+    got = selftest_philox(ctr, key)
+    for i in range(0, n, 37):
+        assert np.array_equal(got[i], oracle.philox4x32_10(ctr[i], key)), i
+
+
+def test_sqrt_correctly_rounded():
+    from paper_2109_04469_amd import selftest_sqrt
+
+    rng = np.random.default_rng(2)
+    x = np.concatenate([
+        rng.uniform(0, 1, 400_000),
+        np.exp(rng.uniform(-700, 700, 400_000)),
+        rng.uniform(0, 1e14, 200_000),  # squared speeds of the method
+        np.array([0.0, 1.0, 2.0, 4.0, np.finfo(float).tiny, np.finfo(float).max]),
+    ])
+    # numpy's sqrt is the IEEE correctly rounded square root
+    assert np.array_equal(selftest_sqrt(x), np.sqrt(x))
+
+
+@pytest.mark.parametrize("n", [1, 1023, 1024, 5000, 37_001])
+def test_deposit_exact(n):
+    p = params(n_cells=128, capacity=(40_000, 40_000))
+    xs = xsec.argon_synthetic()
+    L = p["gap_m"]
+    rng = np.random.default_rng(n)
+    x = rng.uniform(0, L, n)
+    x[: min(n, 3)] = [0.0, L, 0.5 * L][: min(n, 3)]
+    z = np.zeros(n)
+    init = {0: (x, z, z, z), 1: (x[::-1].copy(), z, z, z)}
+    gpu, ora = pair(p, xs, init)
+    ora.deposit()
+    fg, fo = gpu.get_field(), ora.get_field()
+    assert np.array_equal(fg["dep_e"], fo["dep_e"])
+    assert np.array_equal(fg["dep_i"], fo["dep_i"])
+    assert int(fg["dep_e"].sum()) == n * 2**32
+
+
+def _field_case(mode_flags, n_cells, seed):
+    p = params(n_cells=n_cells, flags=NO_COLL | mode_flags, capacity=(60_000, 60_000), sort_interval=0)
+    xs = xsec.argon_synthetic()
+    rng = np.random.default_rng(seed)
+    L = p["gap_m"]
+    # non-uniform charge: electrons depleted near the walls (sheath-like)
+    xe = rng.uniform(0.1 * L, 0.9 * L, 20_000)
+    xi = rng.uniform(0, L, 21_000)
+    init = {0: (xe, *np.zeros((3, xe.size))), 1: (xi, *np.zeros((3, xi.size)))}
+    gpu, ora = pair(p, xs, init, step=7)
+    gpu.step(1)
+    ora.step(1)
+    return gpu.get_field(), ora.get_field(), p
+
+
+@pytest.mark.parametrize("n_cells", [128, 512, 2048])
+def test_field_thomas_bitwise(n_cells):
+    fg, fo, _ = _field_case(THOMAS, n_cells, 5)
+    assert np.array_equal(fg["rho"], fo["rho"])
+    assert np.array_equal(fg["phi"], fo["phi"])
+    assert np.array_equal(fg["E"], fo["E"])
+
+
+@pytest.mark.parametrize("n_cells", [128, 512, 2048])
+def test_field_exact_solver_within_rounding(n_cells):
+    # The default solver sums the integer deposits exactly and rounds a few
+    # times per node; the oracle's Thomas recurrence accumulates rounding over
+    # the grid. Both are within a few hundred ulps of max|phi| (max|E| dx).
+    fg, fo, p = _field_case(0, n_cells, 6)
+    assert np.array_equal(fg["rho"], fo["rho"])
+    eps = np.finfo(float).eps
+    nx = n_cells + 1
+    phis = np.max(np.abs(fo["phi"]))
+    assert np.max(np.abs(fg["phi"] - fo["phi"])) < 8 * nx * eps * phis
+    dx = p["gap_m"] / n_cells
+    Es = max(np.max(np.abs(fo["E"])), phis / dx)
+    assert np.max(np.abs(fg["E"] - fo["E"])) < 8 * nx * eps * Es
+
+
+def _near_wall_state(n, L, vscale, reach, seed, species, frac=0.05):
+    """Uniform particles with Gaussian velocities; a fraction sits within
+    `reach` of a wall and moves towards it."""
+    rng = np.random.default_rng([seed, species, 5])
+    x = rng.uniform(0, L, n)
+    v = rng.normal(0, vscale, (3, n))
+    k = int(frac * n)
+    idx = rng.choice(n, size=k, replace=False)
+    side = rng.integers(0, 2, k)
+    d = rng.uniform(0, reach, k)
+    x[idx] = np.where(side == 0, d, L - d)
+    v[0, idx] = np.where(side == 0, -1, 1) * np.abs(v[0, idx])
+    return (x, v[0].copy(), v[1].copy(), v[2].copy())
+
+
+def _single_step_case(n, seed, step, subcycle, flags, R=0.3, gamma=0.25, n_cells=128):
+    p = params(n_cells=n_cells, reflection=R, gamma_see=gamma, ion_subcycle=subcycle,
+               flags=flags | RECORD, capacity=(3 * n + 64, 3 * n + 64), sort_interval=0,
+               pressure_pa=30.0)
+    xs = xsec.argon_synthetic()
+    L = p["gap_m"]
+    dt = 1.0 / (p["rf_freq_hz"] * p["steps_per_cycle"])
+    ve = _vth(3.0, ME)
+    vi = _vth(50.0, MAR)
+    e = _near_wall_state(n, L, ve, ve * dt, seed, 0)
+    i = _near_wall_state(n + 17, L, vi, vi * dt * subcycle, seed, 1)
+    rng = np.random.default_rng(seed + 1)
+    E = rng.normal(0, 3e4, n_cells + 1) if flags & FIXED_E else None
+    return p, xs, {0: e, 1: i}, E, L, ve, vi
+
+
+@pytest.mark.parametrize("n,seed,step,subcycle", [
+    (5000, 1, 0, 1), (20_011, 2, 3, 1), (7_777, 3, 10, 5), (7_777, 4, 11, 5), (1, 5, 0, 1)])
+def test_single_step_fixed_field(n, seed, step, subcycle):
+    p, xs, init, E, L, ve, vi = _single_step_case(n, seed, step, subcycle, FIXED_E)
+    gpu, ora = pair(p, xs, init, step=step, fixed_E=E)
+    gpu.step(1)
+    ora.step(1)
+    for sp, vs in ((0, ve), (1, vi)):
+        assert np.array_equal(gpu.decisions(sp), ora.decisions(sp)), f"decisions species {sp}"
+        assert_state_close(gpu.get_state(sp), ora.get_state(sp), L, vs, what=f"species {sp}")
+    assert np.array_equal(gpu.counters(), ora.counters())
+    fg, fo = gpu.get_field(), (ora.deposit() or ora.get_field())
+    assert np.array_equal(fg["dep_e"], fo["dep_e"])
+    assert np.array_equal(fg["dep_i"], fo["dep_i"])
+
+
+def test_single_step_with_field_solve_thomas():
+    # the whole step including deposit and Thomas solve, from an evolved state
+    w = workloads.scaled(workloads.get("c1_small"), 6000)
+    p = dict(w["params"], flags=RECORD | THOMAS, gamma_see=0.2, reflection=0.3, sort_interval=10)
+    xs = xsec.argon_synthetic()
+    import oracle as O
+
+    warm = O.Oracle(p, xs)
+    init = state.initial_state(w, seed=9)
+    for sp in (0, 1):
+        warm.set_state(sp, *init[sp], step=0)
+    assert warm.step(40) == 0
+    st = {sp: warm.get_state(sp) for sp in (0, 1)}
+    gpu, ora = pair(p, xs, st, step=40)
+    gpu.step(1)
+    ora.step(1)
+    assert np.array_equal(gpu.get_field()["E"], ora.get_field()["E"])
+    for sp, vs in ((0, _vth(2.0, ME)), (1, _vth(0.03, MAR))):
+        assert np.array_equal(gpu.decisions(sp), ora.decisions(sp))
+        assert_state_close(gpu.get_state(sp), ora.get_state(sp), p["gap_m"], vs, what=f"sp {sp}")
+
+
+def test_multi_step_bitwise_without_collisions():
+    # No transcendental enters a collisionless step with R > 0 and gamma = 0:
+    # 300 steps with Thomas solves, wall reflections, compaction and cell sorts
+    # must reproduce the oracle bit for bit.
+    w = workloads.scaled(workloads.get("c1_small"), 8000)
+    p = dict(w["params"], flags=NO_COLL | THOMAS, reflection=0.4, gamma_see=0.0, sort_interval=25)
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w, seed=4)
+    gpu, ora = pair(p, xs, init)
+    for _ in range(3):
+        gpu.step(100)
+        assert ora.step(100) == 0
+        for sp in (0, 1):
+            assert_state_equal(gpu.get_state(sp), ora.get_state(sp), what=f"species {sp}")
+    assert np.array_equal(gpu.counters(), ora.counters())
+
+
+def test_multi_step_default_solver_close():
+    # Same run with the default (exact-integer) Poisson solver: states agree
+    # to rounding level after 60 steps, counts and wall events exactly.
+    w = workloads.scaled(workloads.get("c1_small"), 8000)
+    p = dict(w["params"], flags=NO_COLL, reflection=0.4, gamma_see=0.0, sort_interval=25)
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w, seed=4)
+    gpu, ora = pair(p, xs, init)
+    gpu.step(60)
+    assert ora.step(60) == 0
+    for sp, vs in ((0, _vth(2.0, ME)), (1, _vth(0.03, MAR))):
+        assert_state_close(gpu.get_state(sp), ora.get_state(sp), p["gap_m"], vs, rtol=1e-9,
+                           what=f"species {sp}")
+    assert np.array_equal(gpu.counters(), ora.counters())
+
+
+def test_determinism_and_exact_resume():
+    w = workloads.scaled(workloads.get("c1_small"), 6000)
+    p = dict(w["params"], sort_interval=20)
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w, seed=8)
+    from paper_2109_04469_amd import Discharge
+
+    def run(split):
+        d = Discharge(p, xs)
+        for sp in (0, 1):
+            d.set_state(sp, *init[sp], step=0)
+        if split:
+            d.step(50)
+            st = {sp: d.get_state(sp) for sp in (0, 1)}
+            s = d.step_index
+            d = Discharge(p, xs)
+            for sp in (0, 1):
+                d.set_state(sp, *st[sp], step=s)
+            d.step(50)
+        else:
+            d.step(100)
+        return [d.get_state(sp) for sp in (0, 1)]
+
+    a, b, c = run(False), run(False), run(True)
+    for sp in (0, 1):
+        assert_state_equal(a[sp], b[sp], what="rerun")
+        assert_state_equal(a[sp], c[sp], what="resume")
