@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of the explicit 1D3V PIC/MCC step (arXiv:2109.04469, Sec. 2) on
+one MI355X.
+
+A step is one pass of the whole hot path: field solve, electron particle
+kernel, the sub-cycled ion kernel on its steps and the periodic cell sort.
+The default workload is the large low-pressure discharge: 6.7 cm gap, 2048
+cells, dt = T_RF/8000, 2 Pa, 500 V, gamma = 0.2, R = 0.5, 4M electrons + 4M
+Ar+ in FP64, ions sub-cycled x10, synthetic argon-shaped cross sections,
+starting from a uniform Maxwellian plasma. After `--warmup` steps (default
+two RF cycles) `--steps` steps (default one RF cycle) are timed with inputs
+resident in HBM.
+
+value = particle-steps per second over the timed region (electrons every
+step, ions on their sub-cycled steps), from the library's own push counters.
+roofline: the electron particle kernel, algorithmic traffic 64 B per
+particle-step (x, vx, vy, vz read and written in FP64) divided by its mean
+launch time from HIP events recorded on the library's stream.
+cpu_baseline: the CPU oracle (single thread) on a bounded sample of the same
+workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (push+MCC+CIC) vs HBM roofline; batched & warm-start speedup"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PARTICLE_STEP = 64
+
+DESCRIPTIONS = {
+    "c3_large_lowp": ("gap 6.7 cm, 2048 cells, dt=T_RF/8000, 13.56 MHz, 500 V, 2 Pa, gamma 0.2, R 0.5, "
+                      "4M e + 4M Ar+ fp64, ions sub-cycled x10, synthetic argon cross sections"),
+    "c2_production": ("gap 2.5 cm, 512 cells, dt=T_RF/4000, 13.56 MHz, 300 V, 50 Pa, gamma 0.1, R 0, "
+                      "400k e + 400k Ar+ fp64, synthetic argon cross sections"),
+    "c1_small": ("gap 2.5 cm, 128 cells, dt=T_RF/1000, 13.56 MHz, 100 V, 10 Pa, gamma 0, R 0.2, "
+                 "10k e + 10k Ar+ fp64"),
+}
+
+
+def cpu_baseline(workload, init, xs, nsteps):
+    import oracle
+
+    p = dict(workload["params"])
+    o = oracle.Oracle(p, xs)
+    for sp in (0, 1):
+        o.set_state(sp, *init[sp], step=0)
+    c0 = o.counters()
+    t0 = time.perf_counter()
+    st = o.step(nsteps)
+    t1 = time.perf_counter()
+    c1 = o.counters()
+    ps = int((c1[1] - c0[1]) + (c1[2] - c0[2]))
+    return {
+        "value": ps / (t1 - t0),
+        "unit": "particle-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"first {nsteps} steps of {workload['name']} from its synthetic initial state "
+                  f"({ps} particle-steps, {t1 - t0:.1f} s, status {st})",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: one RF cycle)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: two RF cycles)")
+    ap.add_argument("--workload", default="c3_large_lowp", choices=sorted(DESCRIPTIONS))
+    ap.add_argument("--cpu-steps", type=int, default=50, help="oracle steps for cpu_baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs one discharge on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2109_04469_amd import Discharge
+    from pic_inputs import state, workloads, xsec
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = workloads.get(args.workload)
+    p = dict(w["params"])
+    nt = p["steps_per_cycle"]
+    steps = args.steps if args.steps is not None else nt
+    warmup = args.warmup if args.warmup is not None else 2 * nt
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w)
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    log(f"[bench] {w['name']}: init {w['n_init']} particles")
+    d = Discharge(p, xs, "cuda:0")
+    for sp in (0, 1):
+        d.set_state(sp, *init[sp], step=0)
+    chunk = max(1, nt // 4)
+    done = 0
+    while done < warmup:
+        k = min(chunk, warmup - done)
+        d.step(k)
+        st = d.sync()
+        assert st == 0, f"warm-up step failed: status {st}"
+        done += k
+        log(f"[bench] warm-up {done}/{warmup} steps, e={d.count(0)} i={d.count(1)}")
+
+    if not args.no_timing:
+        d.timing(True)
+        d.get_timing(reset=True)
+    c0 = d.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d.step(steps)
+    st = d.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert st == 0, f"timed steps failed: status {st}"
+    c1 = d.counters()
+    elapsed = t1 - t0
+    pe = int(c1[1] - c0[1])
+    pi = int(c1[2] - c0[2])
+    value = (pe + pi) / elapsed
+    log(f"[bench] timed {steps} steps in {elapsed:.3f} s")
+
+    roof = None
+    kernels = None
+    if not args.no_timing:
+        tm = d.get_timing()
+        kernels = {k: {"ms_total": v[0], "launches": v[1],
+                       "us_per_launch": (1e3 * v[0] / v[1]) if v[1] else None} for k, v in tm.items()}
+        ems, en = tm["electron"]
+        if en:
+            avg_s = ems / en * 1e-3
+            bytes_per_launch = BYTES_PER_PARTICLE_STEP * pe / en
+            achieved = bytes_per_launch / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "kernel": "k_particle<electron>", "bytes_per_launch": bytes_per_launch,
+                    "avg_launch_us": avg_s * 1e6}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w['name']}: {DESCRIPTIONS[w['name']]}",
+            "particles_e": d.count(0), "particles_i": d.count(1),
+            "particle_steps_e": pe, "particle_steps_i": pi,
+            "n_cells": p["n_cells"], "steps_per_cycle": nt, "ion_subcycle": p["ion_subcycle"],
+            "sort_interval": p["sort_interval"], "parallelism": "single GPU",
+        },
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
+        out["cpu_baseline"] = cpu_baseline(w, init, xs, args.cpu_steps)
+    _ = np
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -19,8 +19,8 @@
  *  - Streams: every device operation is enqueued on the hipStream_t given to
  *    pic_init (NULL = the legacy default stream). pic_step is asynchronous;
  *    the calls documented as "synchronises" wait for that stream.
- *  - Errors found on the device (non-finite state, capacity overflow, speed
- *    beyond a collision table) are latched in a device error word and
+ *  - Errors found on the device (non-finite state, capacity overflow) are
+ *    latched in a device error word and
  *    returned by the next synchronising call. After a latched error the
  *    particle state is unspecified; recover with pic_set_state.
  *  - A handle may be used by one host thread at a time.
@@ -42,7 +42,8 @@ extern "C" {
 #define PIC_EHIP       -2 /* a HIP runtime call failed (no GPU, launch error) */
 #define PIC_ECAPACITY  -3 /* a species outgrew its capacity                   */
 #define PIC_EUNSTABLE  -4 /* a non-finite position, velocity or field value   */
-#define PIC_ETABLE     -5 /* a collision candidate's speed is beyond its table */
+#define PIC_ETABLE     -5 /* reserved (speeds beyond a table are counted, see
+                             PIC_CNT_BEYOND_TABLE)                            */
 #define PIC_ESTATE     -6 /* call not valid in the handle's current state     */
 
 /* ---- species ----------------------------------------------------------- */
@@ -76,7 +77,8 @@ enum {
   PIC_CNT_I_ISOTROPIC,
   PIC_CNT_I_BACKWARD,
   PIC_CNT_REFLECT_LOST,  /* reflected but still outside: removed             */
-  PIC_CNT_RESERVED,
+  PIC_CNT_BEYOND_TABLE,  /* candidates faster than the last table speed: the
+                            last table entry is used                        */
   PIC_NCOUNTERS
 };
 
@@ -225,6 +227,17 @@ int pic_get_counters(pic_handle* h, int64_t* counters);
  * slots that existed at its start (host or device buffer of `cap` bytes).
  * *n receives the number of slots. Synchronises. */
 int pic_get_decisions(pic_handle* h, int species, uint8_t* codes, int64_t cap, int64_t* n);
+
+/* Per-kernel timing with HIP events recorded on the handle's stream around
+ * every launch while on != 0 (measurement surface; it adds two event
+ * records per launch). Kernels: PIC_TIMER_FIELD, _ELECTRON, _ION, _SORT. */
+enum { PIC_TIMER_FIELD = 0, PIC_TIMER_ELECTRON, PIC_TIMER_ION, PIC_TIMER_SORT, PIC_NTIMERS };
+int pic_timing(pic_handle* h, int on);
+
+/* Synchronises and returns, per timer, the summed kernel time in ms
+ * (ms[PIC_NTIMERS]) and the number of timed launches (launches[PIC_NTIMERS]);
+ * reset != 0 clears them. */
+int pic_get_timing(pic_handle* h, double* ms, int64_t* launches, int reset);
 
 /* Copies the derived quantities of pic_init (host). */
 int pic_get_derived(const pic_handle* h, pic_derived* d);

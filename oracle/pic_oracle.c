@@ -38,7 +38,6 @@ void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 #define ORA_EINVAL -1
 #define ORA_ECAPACITY -3
 #define ORA_EUNSTABLE -4
-#define ORA_ETABLE -5
 
 /* flags */
 #define F_NO_FIELD 1u
@@ -49,7 +48,7 @@ void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 
 enum { C_STEPS = 0, C_E_PUSHED, C_I_PUSHED, C_E_ABSORBED, C_E_REFLECTED, C_I_ABSORBED,
        C_SE_EMITTED, C_E_CAND, C_E_ELASTIC, C_E_EXC, C_E_ION, C_I_CAND, C_I_ISO, C_I_BACK,
-       C_REFLECT_LOST, C_RESERVED, NCOUNT };
+       C_REFLECT_LOST, C_BEYOND, NCOUNT };
 
 typedef struct {
   double gap_m, pressure_pa, gas_temp_k, rf_voltage_v, rf_freq_hz;
@@ -474,10 +473,15 @@ static void plist_push(plist* l, double x, double vx, double vy, double vz) {
 }
 
 /* Linear interpolation of a cumulative collision-frequency table at speed v.
- * Returns 0 and fills nu[] when v is inside the table. */
+ * Beyond the last table speed the last entry is used (a constant frequency,
+ * still bounded by nu_max); the function then returns 1 so the event can be
+ * counted. */
 static int table_lookup(const ora_sim* s, int sp, double v, double* nu) {
   double tv = v * s->inv_dv[sp];
-  if (!(tv < (double)(s->p.ntab - 1))) return -1;
+  if (!(tv < (double)(s->p.ntab - 1))) {
+    for (int q = 0; q < s->nproc[sp]; q++) nu[q] = s->cum[sp][q][s->p.ntab - 1];
+    return 1;
+  }
   int64_t k = (int64_t)tv;
   double t = tv - (double)k;
   for (int q = 0; q < s->nproc[sp]; q++) nu[q] = (1.0 - t) * s->cum[sp][q][k] + t * s->cum[sp][q][k + 1];
@@ -630,10 +634,8 @@ int ora_step(ora_sim* s, int64_t nsteps) {
             s->counters[C_E_CAND]++;
             double v2 = vx * vx + vy * vy + vz * vz;
             double speed = sqrt(v2);
-            if (table_lookup(s, 0, speed, nu) != 0) {
-              s->err = s->err ? s->err : ORA_ETABLE;
-              code |= 1 << 3;
-            } else {
+            if (table_lookup(s, 0, speed, nu) != 0) s->counters[C_BEYOND]++;
+            {
               double r = u01(r0[2]) * s->numax[0];
               uint32_t r1[4];
               if (r < nu[0]) {
@@ -707,10 +709,8 @@ int ora_step(ora_sim* s, int64_t nsteps) {
             double ax = s->sig_g * n1, ay = s->sig_g * n2, az = s->sig_g * n3;
             double gx = vx - ax, gy = vy - ay, gz = vz - az;
             double g = sqrt(gx * gx + gy * gy + gz * gz);
-            if (table_lookup(s, 1, g, nu) != 0) {
-              s->err = s->err ? s->err : ORA_ETABLE;
-              code |= 1 << 3;
-            } else {
+            if (table_lookup(s, 1, g, nu) != 0) s->counters[C_BEYOND]++;
+            {
               double r = u01(r0[2]) * s->numax[1];
               if (r < nu[0]) {
                 /* isotropic elastic in the centre-of-mass frame (equal masses) */

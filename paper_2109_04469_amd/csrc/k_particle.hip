@@ -238,27 +238,36 @@ __global__ __launch_bounds__(kBlock) void k_particle(PartArgs a) {
               const double gz = vz - a.sig_g * n3;
               g = sqrt(gx * gx + gy * gy + gz * gz);
             }
+            // cumulative frequencies interpolated in speed; beyond the last
+            // table speed the last entry is used (still <= nu_max) and the
+            // event is counted
             const double tv = g * a.inv_dv;
             uint32_t proc = 1;
-            if (!(tv < (double)(a.ntab - 1))) {
-              latch_error(ctl, kErrTable);
+            const double r = u01(r0.z) * a.numax;
+            const double* c0 = a.cum;
+            const double* c1 = a.cum + a.ntab;
+            const double* c2 = a.cum + 2 * a.ntab;
+            double nu0, nu1;
+            int kk = a.ntab - 1;
+            double tt = 0.0;
+            const bool inside = tv < (double)(a.ntab - 1);
+            if (inside) {
+              kk = (int)tv;
+              tt = tv - (double)kk;
+              nu0 = (1.0 - tt) * c0[kk] + tt * c0[kk + 1];
+              nu1 = (1.0 - tt) * c1[kk] + tt * c1[kk + 1];
             } else {
-              const int kk = (int)tv;
-              const double tt = tv - (double)kk;
-              const double r = u01(r0.z) * a.numax;
-              const double* c0 = a.cum;
-              const double nu0 = (1.0 - tt) * c0[kk] + tt * c0[kk + 1];
-              const double* c1 = a.cum + a.ntab;
-              const double nu1 = (1.0 - tt) * c1[kk] + tt * c1[kk + 1];
-              if (r < nu0) {
-                proc = 2;
-              } else if (r < nu1) {
-                proc = 3;
-              } else if (SP == 0) {
-                const double* c2 = a.cum + 2 * a.ntab;
-                const double nu2 = (1.0 - tt) * c2[kk] + tt * c2[kk + 1];
-                if (r < nu2) proc = 4;
-              }
+              atomicAdd(&s_cnt[C_BEYOND_TABLE], 1ull);
+              nu0 = c0[kk];
+              nu1 = c1[kk];
+            }
+            if (r < nu0) {
+              proc = 2;
+            } else if (r < nu1) {
+              proc = 3;
+            } else if (SP == 0) {
+              const double nu2 = inside ? (1.0 - tt) * c2[kk] + tt * c2[kk + 1] : c2[kk];
+              if (r < nu2) proc = 4;
             }
             c |= proc << 3;
             if (SP == 0) {

@@ -102,6 +102,41 @@ int hip_status(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EHIP; }
     if (_e != hipSuccess) return PIC_EHIP;   \
   } while (0)
 
+// Starts a timed launch: returns the event index or -1 when timing is off.
+int timer_begin(pic_handle* h) {
+  if (!h->timing) return -1;
+  const size_t need = 2 * (h->ev_used.size() + 1);
+  while (h->ev_pool.size() < need) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    h->ev_pool.push_back(e);
+  }
+  const int idx = (int)(2 * h->ev_used.size());
+  if (hipEventRecord(h->ev_pool[idx], h->stream) != hipSuccess) return -1;
+  return idx;
+}
+
+void timer_end(pic_handle* h, int timer, int idx) {
+  if (idx < 0) return;
+  if (hipEventRecord(h->ev_pool[idx + 1], h->stream) == hipSuccess)
+    h->ev_used.emplace_back(timer, idx);
+}
+
+// Folds the recorded event pairs into the per-timer sums (synchronises).
+int timer_collect(pic_handle* h) {
+  if (h->ev_used.empty()) return PIC_OK;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return PIC_EHIP;
+  for (const auto& u : h->ev_used) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev_pool[u.second], h->ev_pool[u.second + 1]) != hipSuccess)
+      return PIC_EHIP;
+    h->t_ms[u.first] += ms;
+    h->t_n[u.first] += 1;
+  }
+  h->ev_used.clear();
+  return PIC_OK;
+}
+
 int latched(pic_handle* h) {
   uint32_t err = 0;
   HIP_TRY(hipMemcpyAsync(&err, &h->ctl->err, sizeof(err), hipMemcpyDeviceToHost, h->stream));
@@ -109,7 +144,6 @@ int latched(pic_handle* h) {
   if (err & kErrLookback) return PIC_EHIP;
   if (err & kErrUnstable) return PIC_EUNSTABLE;
   if (err & kErrCapacity) return PIC_ECAPACITY;
-  if (err & kErrTable) return PIC_ETABLE;
   return PIC_OK;
 }
 
@@ -202,7 +236,9 @@ int sort_species(pic_handle* h, int sp) {
   a.inv_dx = h->inv_dx;
   a.nx = h->nx;
   a.nblocks = h->sort_blocks;
+  const int ev = timer_begin(h);
   HIP_TRY(launch_sort(a, h->stream));
+  timer_end(h, PIC_TIMER_SORT, ev);
   h->cur[sp] = out;
   return PIC_OK;
 }
@@ -218,7 +254,7 @@ const char* pic_strerror(int s) {
     case PIC_EHIP: return "HIP runtime error (no GPU, or a launch failed)";
     case PIC_ECAPACITY: return "a species outgrew its capacity";
     case PIC_EUNSTABLE: return "non-finite position, velocity or field";
-    case PIC_ETABLE: return "collision candidate beyond its cross-section table";
+    case PIC_ETABLE: return "reserved";
     case PIC_ESTATE: return "call not valid in the current state";
     default: return "unknown status";
   }
@@ -493,19 +529,30 @@ int pic_step(pic_handle* h, int64_t n_steps) {
     f.mode = mode;
     f.measuring = h->measuring;
     f.parity = par;
+    int ev = timer_begin(h);
     HIP_TRY(launch_field(f, h->stream));
+    timer_end(h, PIC_TIMER_FIELD, ev);
 
     const int m = h->measuring ? 1 : 0;
     PartArgs ae = particle_args(h, 0, par);
+    ev = timer_begin(h);
     HIP_TRY(launch_particles(0, m == 1, ae, h->grid[0][m], h->lds[m], h->stream));
+    timer_end(h, PIC_TIMER_ELECTRON, ev);
     h->cur[0] ^= 1;
     if (ion_step) {
       PartArgs ai = particle_args(h, 1, par);
+      ev = timer_begin(h);
       HIP_TRY(launch_particles(1, false, ai, h->grid[1][0], h->lds[0], h->stream));
+      timer_end(h, PIC_TIMER_ION, ev);
       h->cur[1] ^= 1;
       h->cur_hi ^= 1;
     }
     h->step += 1;
+    // keep the event backlog bounded
+    if (h->ev_used.size() >= 4096) {
+      const int st = timer_collect(h);
+      if (st) return st;
+    }
     if (p.sort_interval > 0 && h->step % p.sort_interval == 0) {
       int s = sort_species(h, 0);
       if (s) return s;
@@ -615,9 +662,31 @@ int pic_get_decisions(pic_handle* h, int species, uint8_t* codes, int64_t cap, i
   return latched(h);
 }
 
+int pic_timing(pic_handle* h, int on) {
+  if (!h) return PIC_EINVAL;
+  h->timing = on ? 1 : 0;
+  return PIC_OK;
+}
+
+int pic_get_timing(pic_handle* h, double* ms, int64_t* launches, int reset) {
+  if (!h) return PIC_EINVAL;
+  const int st = timer_collect(h);
+  if (st) return st;
+  for (int i = 0; i < PIC_NTIMERS; ++i) {
+    if (ms) ms[i] = h->t_ms[i];
+    if (launches) launches[i] = h->t_n[i];
+    if (reset) {
+      h->t_ms[i] = 0.0;
+      h->t_n[i] = 0;
+    }
+  }
+  return PIC_OK;
+}
+
 void pic_free(pic_handle* h) {
   if (!h) return;
   (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   delete h;
 }
 

@@ -26,7 +26,6 @@ constexpr int64_t kOne32 = 4294967296LL;
 // latched device error bits
 constexpr uint32_t kErrUnstable = 1u;
 constexpr uint32_t kErrCapacity = 2u;
-constexpr uint32_t kErrTable = 4u;
 constexpr uint32_t kErrLookback = 8u;  // a tile's prefix wait hit its bound
 
 // decision code bits (per pushed slot)
@@ -35,7 +34,7 @@ constexpr uint8_t kCodePushed = 0x80;
 enum Counter {
   C_STEPS = 0, C_E_PUSHED, C_I_PUSHED, C_E_ABSORBED, C_E_REFLECTED, C_I_ABSORBED,
   C_SE_EMITTED, C_E_CAND, C_E_ELASTIC, C_E_EXC, C_E_ION, C_I_CAND, C_I_ISO, C_I_BACK,
-  C_REFLECT_LOST, C_RESERVED, NCOUNTERS
+  C_REFLECT_LOST, C_BEYOND_TABLE, NCOUNTERS
 };
 
 // Control block in device memory. Counts are double-buffered by step parity:

@@ -174,4 +174,10 @@ struct pic_handle {
   uint32_t epoch;
   int grid[2][2];     // [species][measure]
   size_t lds[2];      // [measure]
+  // opt-in kernel timing: event pairs recorded around launches
+  int timing;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_used;  // (timer, index of start event)
+  double t_ms[PIC_NTIMERS];
+  int64_t t_n[PIC_NTIMERS];
 };

@@ -174,6 +174,15 @@ class Discharge:
         check(self.L.pic_get_decisions(self.h, species, _ptr(buf), cap, ctypes.byref(n)), "pic_get_decisions")
         return buf[: n.value].copy()
 
+    def timing(self, on=True):
+        check(self.L.pic_timing(self.h, 1 if on else 0), "pic_timing")
+
+    def get_timing(self, reset=False):
+        ms = np.zeros(capi.NTIMERS)
+        n = np.zeros(capi.NTIMERS, np.int64)
+        check(self.L.pic_get_timing(self.h, _ptr(ms), _ptr(n), 1 if reset else 0), "pic_get_timing")
+        return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(capi.TIMER_NAMES)}
+
     def derived(self):
         d = PicDerived()
         check(self.L.pic_get_derived(self.h, ctypes.byref(d)), "pic_get_derived")

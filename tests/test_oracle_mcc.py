@@ -192,3 +192,25 @@ def test_cross_section_scale_matches_paper_collision_probabilities(ora):
         sim = ora.Oracle(params(pressure_pa=10.0, steps_per_cycle=Nt), xs)
         pc = sim.derived()["p_coll_e"]
         assert abs(pc / target - 1) < 0.15, (Nt, pc)
+
+
+def test_speed_beyond_table_uses_last_entry(ora):
+    # Candidates faster than the last table speed collide with the last
+    # tabulated frequency (<= nu_max, so the null-collision bound holds) and
+    # are counted. With a constant sigma, nu(v_last) = nu_max: every
+    # candidate is a real collision.
+    vtop = 1e6
+    xs = table_for(vtop, 1e5, n=65, sig_e=(1e-19, 0.0, 0.0))
+    p = params(gap_m=1e3, n_cells=16, pressure_pa=300.0, flags=NO_FIELD | RECORD, sort_interval=0,
+               capacity=(20_000, 8))
+    sim = ora.Oracle(p, xs)
+    n = 20_000
+    rng = np.random.default_rng(15)
+    sim.set_state(0, rng.uniform(400, 600, n), *iso_velocities(n, 3 * vtop, rng))
+    sim.set_state(1, np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0))
+    assert sim.step(1) == 0
+    code = _code_coll(sim.decisions(0))
+    c = sim.counters()
+    assert c[15] == (code > 0).sum() > 0      # every candidate was beyond the table
+    assert (code == 1).sum() == 0             # and none was a null event
+    assert c[8] == (code == 2).sum()
