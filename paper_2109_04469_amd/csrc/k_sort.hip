@@ -4,7 +4,8 @@
 // field gathers stay local. Stable, so the result is a pure function of the
 // input order. Three kernels:
 //   count   per-chunk key histograms (LDS), written key-major
-//   scan    exclusive scan over (key, chunk) -> output offsets
+//   scan    exclusive scan over (key, chunk) -> output offsets (three
+//           parallel kernels)
 //   scatter each chunk walks its particles in order; lanes with equal keys
 //           are ranked with wave ballots and the waves of a workgroup take
 //           their offsets in turn, which preserves the input order.
@@ -13,7 +14,6 @@
 namespace pic {
 
 constexpr int kSortThreads = 256;
-constexpr int kScanThreads = 1024;
 
 __device__ __forceinline__ void chunk_range(int64_t n, int nblocks, int b, int64_t& lo,
                                             int64_t& hi) {
@@ -38,39 +38,71 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(SortArgs a) {
     a.cnt[(size_t)k * a.nblocks + blockIdx.x] = sh[k];
 }
 
-// Exclusive scan of total = nkeys * nblocks counters, in place, one
-// workgroup: each wave owns a contiguous segment read 64 entries at a time.
-__global__ __launch_bounds__(kScanThreads) void k_sort_scan(SortArgs a) {
-  __shared__ uint32_t s_wave[kScanThreads / kWave + 1];
-  const int64_t total = (int64_t)(a.nx - 1) * a.nblocks;
-  const int nw = kScanThreads / kWave;
-  const int wave = threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t seg = ((total + nw - 1) / nw + kWave - 1) / kWave * kWave;
-  const int64_t lo = (int64_t)wave * seg;
-  int64_t hi = lo + seg;
+// Exclusive scan of the nkeys * nblocks counters in place, in three
+// parallel kernels: per-segment sums, a scan of the segment sums, and the
+// per-segment rescan with its base.
+constexpr int kScanSegs = 256;
+
+__device__ __forceinline__ void seg_range(int64_t total, int seg, int64_t& lo, int64_t& hi) {
+  const int64_t len = (total + kScanSegs - 1) / kScanSegs;
+  lo = (int64_t)seg * len;
+  hi = lo + len;
   if (hi > total) hi = total;
+  if (lo > total) lo = total;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_scan_reduce(SortArgs a) {
+  __shared__ uint32_t s_w[kSortThreads / kWave];
+  const int64_t total = (int64_t)(a.nx - 1) * a.nblocks;
+  int64_t lo, hi;
+  seg_range(total, blockIdx.x, lo, hi);
   uint32_t sum = 0;
-  for (int64_t i = lo + lane; i < hi; i += kWave) sum += a.cnt[i];
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads) sum += a.cnt[i];
   sum = wave_sum<unsigned int>(sum);
-  if (lane == 0) s_wave[wave] = sum;
+  if ((threadIdx.x & (kWave - 1)) == 0) s_w[threadIdx.x / kWave] = sum;
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int w = 0; w < nw; ++w) {
-      const uint32_t v = s_wave[w];
-      s_wave[w] = run;
-      run += v;
-    }
+    uint32_t t = 0;
+    for (int w = 0; w < kSortThreads / kWave; ++w) t += s_w[w];
+    a.seg[blockIdx.x] = t;
   }
+}
+
+__global__ __launch_bounds__(kScanSegs) void k_scan_top(SortArgs a) {
+  __shared__ uint32_t s_w[kScanSegs / kWave];
+  const uint32_t v = a.seg[threadIdx.x];
+  const uint32_t inc = wave_incl_scan<unsigned int>(v);
+  if ((threadIdx.x & (kWave - 1)) == kWave - 1) s_w[threadIdx.x / kWave] = inc;
   __syncthreads();
-  uint32_t run = s_wave[wave];
-  for (int64_t i0 = lo; i0 < hi; i0 += kWave) {
-    const int64_t i = i0 + lane;
+  uint32_t base = 0;
+  for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) base += s_w[w];
+  a.seg[threadIdx.x] = base + inc - v;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_scan_down(SortArgs a) {
+  __shared__ uint32_t s_w[kSortThreads / kWave];
+  const int64_t total = (int64_t)(a.nx - 1) * a.nblocks;
+  int64_t lo, hi;
+  seg_range(total, blockIdx.x, lo, hi);
+  lo = uniform64(lo);
+  hi = uniform64(hi);
+  const int wave = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  uint32_t run = a.seg[blockIdx.x];
+  for (int64_t b0 = lo; b0 < hi; b0 += kSortThreads) {
+    const int64_t i = b0 + threadIdx.x;
     const uint32_t v = i < hi ? a.cnt[i] : 0u;
     const uint32_t inc = wave_incl_scan<unsigned int>(v);
-    if (i < hi) a.cnt[i] = run + inc - v;
-    run += __shfl(inc, kWave - 1, kWave);
+    if (lane == kWave - 1) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t wbase = 0, tot = 0;
+    for (int w = 0; w < kSortThreads / kWave; ++w) {
+      if (w < wave) wbase += s_w[w];
+      tot += s_w[w];
+    }
+    if (i < hi) a.cnt[i] = run + wbase + inc - v;
+    run += tot;
+    __syncthreads();
   }
 }
 
@@ -128,7 +160,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs a) {
 hipError_t launch_sort(const SortArgs& a, hipStream_t s) {
   const size_t lds = (size_t)(a.nx - 1) * sizeof(uint32_t);
   hipLaunchKernelGGL(k_sort_count, dim3(a.nblocks), dim3(kSortThreads), lds, s, a);
-  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kScanThreads), 0, s, a);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(kScanSegs), dim3(kSortThreads), 0, s, a);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanSegs), 0, s, a);
+  hipLaunchKernelGGL(k_scan_down, dim3(kScanSegs), dim3(kSortThreads), 0, s, a);
   hipLaunchKernelGGL(k_sort_scatter, dim3(a.nblocks), dim3(kSortThreads), lds, s, a);
   return hipGetLastError();
 }

@@ -20,7 +20,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t ctl, part[2][2][4], codes[2], tstat[2], dep_e[2], dep_i[2], rho, phi, E, cum[2], th_cp,
-      th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, sort_cnt, total;
+      th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, sort_cnt, sort_seg, total;
   int64_t max_tiles[2];
   int sort_blocks;
 };
@@ -90,6 +90,7 @@ Layout make_layout(const pic_params* p, const pic_xsec* xs) {
   if (sb > 512) sb = 512;
   L.sort_blocks = sb;
   L.sort_cnt = take((size_t)sb * (size_t)(nx - 1) * sizeof(uint32_t));
+  L.sort_seg = take(256 * sizeof(uint32_t));
   L.total = off;
   return L;
 }
@@ -233,6 +234,7 @@ int sort_species(pic_handle* h, int sp) {
   a.count = sp == 0 ? &h->ctl->n_e[h->step & 1] : &h->ctl->n_i[h->step & 1];
   a.cap = h->p.capacity[sp];
   a.cnt = h->sort_cnt;
+  a.seg = h->sort_seg;
   a.inv_dx = h->inv_dx;
   a.nx = h->nx;
   a.nblocks = h->sort_blocks;
@@ -383,6 +385,7 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
   h->acc_ew = reinterpret_cast<double*>(w + L.acc_ew);
   h->eepf = reinterpret_cast<unsigned long long*>(w + L.eepf);
   h->sort_cnt = reinterpret_cast<uint32_t*>(w + L.sort_cnt);
+  h->sort_seg = reinterpret_cast<uint32_t*>(w + L.sort_seg);
   h->sort_blocks = L.sort_blocks;
   h->step = 0;
   h->cur[0] = h->cur[1] = 0;

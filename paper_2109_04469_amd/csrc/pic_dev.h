@@ -14,7 +14,10 @@
 namespace pic {
 
 constexpr int kBlock = 256;          // threads per particle workgroup (4 waves)
-constexpr int kPPT = 4;              // particles per thread per tile
+#ifndef PIC_PPT
+#define PIC_PPT 8
+#endif
+constexpr int kPPT = PIC_PPT;        // particles per thread per tile
 constexpr int kTile = kBlock * kPPT;  // particles per tile
 constexpr int kWave = 64;
 

@@ -108,6 +108,7 @@ struct SortArgs {
   const int64_t* count;  // device count of the species
   int64_t cap;           // capacity of src/dst
   uint32_t* cnt;         // [nkeys][nblocks]
+  uint32_t* seg;         // scan segment sums (256)
   double inv_dx;
   int nx;
   int nblocks;
@@ -164,6 +165,7 @@ struct pic_handle {
   double* acc_ew;
   unsigned long long* eepf;
   uint32_t* sort_cnt;
+  uint32_t* sort_seg;
   int sort_blocks;
   // host-side schedule state
   int64_t step;
