@@ -13,9 +13,14 @@ resident in HBM.
 
 value = particle-steps per second over the timed region (electrons every
 step, ions on their sub-cycled steps), from the library's own push counters.
-roofline: the electron particle kernel, algorithmic traffic 64 B per
-particle-step (x, vx, vy, vz read and written in FP64) divided by its mean
-launch time from HIP events recorded on the library's stream.
+roofline: the electron particle pass (its decide, emit and rare kernels,
+launched back to back on the library's stream), algorithmic traffic 64 B per
+particle-step (x, vx, vy, vz read and written in FP64) divided by the pass's
+mean duration from HIP events recorded on that stream, over a second window
+of the same length right after the timed one (event records slow a step by a
+few percent, so the timed window itself has none). copy_ref is the
+library's plain streaming copy on 2 x 256 MiB, the achievable-bandwidth
+reference on the same GPU.
 cpu_baseline: the CPU oracle (single thread) on a bounded sample of the same
 workload.
 """
@@ -65,6 +70,28 @@ def cpu_baseline(workload, init, xs, nsteps):
     }
 
 
+def copy_reference(torch, nbytes=1 << 28, reps=20):
+    """Read+write bandwidth of the library's plain streaming copy."""
+    from paper_2109_04469_amd import selftest_copy
+
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        selftest_copy(a, b)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        selftest_copy(a, b)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    assert torch.equal(a, b)
+    return {"GBs": 2 * nbytes / (ms * 1e-3) / 1e9, "bytes_read": nbytes, "bytes_written": nbytes,
+            "us_per_copy": ms * 1e3, "kernel": "k_selftest_copy"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,9 +139,7 @@ def main():
         done += k
         log(f"[bench] warm-up {done}/{warmup} steps, e={d.count(0)} i={d.count(1)}")
 
-    if not args.no_timing:
-        d.timing(True)
-        d.get_timing(reset=True)
+    # timed region: no event records inside it
     c0 = d.counters()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -133,18 +158,38 @@ def main():
     roof = None
     kernels = None
     if not args.no_timing:
-        tm = d.get_timing()
-        kernels = {k: {"ms_total": v[0], "launches": v[1],
-                       "us_per_launch": (1e3 * v[0] / v[1]) if v[1] else None} for k, v in tm.items()}
+        # the same number of steps again with HIP events around the field
+        # kernel, each species' particle pass and each sort (event records
+        # add a few microseconds per step, so they stay out of `value`)
+        d.timing(1)
+        d.get_timing(reset=True)
+        e0 = d.counters()
+        d.step(steps)
+        assert d.sync() == 0
+        e1 = d.counters()
+        tm = d.get_timing(reset=True)
+        pe_w = int(e1[1] - e0[1])
+        # a shorter window with events around every particle kernel too
+        d.timing(2)
+        d.step(min(steps, 400))
+        assert d.sync() == 0
+        tk = d.get_timing(reset=True)
+        d.timing(0)
+        kernels = {k: {"launches": v[1], "us_per_launch": (1e3 * v[0] / v[1]) if v[1] else None}
+                   for k, v in tm.items() if v[1] and k in ("field", "electron", "ion", "sort")}
+        kernels.update({k: {"launches": v[1], "us_per_launch": 1e3 * v[0] / v[1],
+                            "note": "events around each kernel"}
+                        for k, v in tk.items() if v[1] and k.split("_")[0] in ("e", "i")})
         ems, en = tm["electron"]
         if en:
             avg_s = ems / en * 1e-3
-            bytes_per_launch = BYTES_PER_PARTICLE_STEP * pe / en
+            bytes_per_launch = BYTES_PER_PARTICLE_STEP * pe_w / en
             achieved = bytes_per_launch / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "kernel": "k_particle<electron>", "bytes_per_launch": bytes_per_launch,
-                    "avg_launch_us": avg_s * 1e6}
+                    "kernel": "electron particle pass: k_decide<0> + k_emit<0> + k_rare<0>",
+                    "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
+                    "particles_per_launch": pe_w / en, "window_steps": steps}
 
     out = {
         "metric": METRIC,
@@ -169,6 +214,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "cpu_baseline": None,
+        "copy_ref": copy_reference(torch),
     }
     if not args.no_cpu:
         log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")

@@ -228,11 +228,28 @@ int pic_get_counters(pic_handle* h, int64_t* counters);
  * *n receives the number of slots. Synchronises. */
 int pic_get_decisions(pic_handle* h, int species, uint8_t* codes, int64_t cap, int64_t* n);
 
-/* Per-kernel timing with HIP events recorded on the handle's stream around
- * every launch while on != 0 (measurement surface; it adds two event
- * records per launch). Kernels: PIC_TIMER_FIELD, _ELECTRON, _ION, _SORT. */
-enum { PIC_TIMER_FIELD = 0, PIC_TIMER_ELECTRON, PIC_TIMER_ION, PIC_TIMER_SORT, PIC_NTIMERS };
-int pic_timing(pic_handle* h, int on);
+/* Kernel timing with HIP events recorded on the handle's stream
+ * (measurement surface). level 0: off. level 1: two event records around
+ * the field kernel, each species' particle pass (PIC_TIMER_ELECTRON,
+ * PIC_TIMER_ION: its decide, emit and rare kernels back to back, the gaps
+ * between them included) and each species' cell sort (PIC_TIMER_SORT).
+ * level 2: also around every single particle kernel (the _DECIDE, _EMIT and
+ * _RARE timers); the extra records delay the launches they separate, so the
+ * pass timers of level 2 read high. */
+enum {
+  PIC_TIMER_FIELD = 0,
+  PIC_TIMER_ELECTRON,
+  PIC_TIMER_ION,
+  PIC_TIMER_SORT,
+  PIC_TIMER_E_DECIDE,
+  PIC_TIMER_E_EMIT,
+  PIC_TIMER_E_RARE,
+  PIC_TIMER_I_DECIDE,
+  PIC_TIMER_I_EMIT,
+  PIC_TIMER_I_RARE,
+  PIC_NTIMERS
+};
+int pic_timing(pic_handle* h, int level);
 
 /* Synchronises and returns, per timer, the summed kernel time in ms
  * (ms[PIC_NTIMERS]) and the number of timed launches (launches[PIC_NTIMERS]);
@@ -254,14 +271,21 @@ const char* pic_strerror(int status);
  * counters: ctr and out are device arrays of 4n uint32, key is 2 host
  * uint32. The method's random decisions (Sec. 2 steps 5 and 6) draw from
  * this generator keyed by (seed, run) with counter (step, slot,
- * 16*species + purpose, 0). Runs on `stream` (a hipStream_t) and
- * synchronises it. */
+ * 16*species + purpose, 0); the collision-candidacy uniform of slot i is
+ * word i mod 4 of the block (step, i / 4, 16*species + 4, 0). Runs on
+ * `stream` (a hipStream_t) and synchronises it. */
 int pic_selftest_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
                         void* stream);
 
 /* FP64 square root of n device doubles on the device (the wall and
  * collision decisions rely on it being correctly rounded). Synchronises. */
 int pic_selftest_sqrt(const double* in, double* out, int64_t n, void* stream);
+
+/* Plain device-to-device copy of n doubles (n even, both arrays 16-byte
+ * aligned, not overlapping): the reference streaming kernel against which
+ * the particle kernels' bandwidth and HBM traffic counters are read. Only
+ * enqueued on `stream`; does not synchronise. */
+int pic_selftest_copy(const double* in, double* out, int64_t n, void* stream);
 
 #ifdef __cplusplus
 }

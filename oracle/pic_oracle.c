@@ -12,7 +12,10 @@
  * reading taken is stated next to the code (the design notes list them all).
  *
  * Random numbers: Philox4x32-10 keyed by (seed, run) with counter
- * (step, slot, 16*species + purpose, 0); u32 r -> (r + 1/2) 2^-32. The paper
+ * (step, slot, 16*species + purpose, 0); u32 r -> (r + 1/2) 2^-32. The
+ * collision-candidacy uniform, the one draw every particle needs every step,
+ * is word (slot mod 4) of the block with counter (step, slot / 4,
+ * 16*species + 4, 0), so one block serves four consecutive slots. The paper
  * draws from MT19937 (Sec. 2 step 5); a counter-based stream keyed by slot
  * gives every particle-step its own draws independent of execution order.
  */
@@ -107,6 +110,15 @@ static void draw(const ora_sim* s, int64_t slot, int species, int purpose, uint3
 }
 
 static double u01(uint32_t r) { return ((double)r + 0.5) * INV_TWO32; }
+
+/* collision-candidacy word of a slot (purpose 4, shared by four slots) */
+static uint32_t candidacy_word(const ora_sim* s, int64_t slot, int species) {
+  uint32_t ctr[4] = {(uint32_t)s->step, (uint32_t)(slot >> 2), (uint32_t)(16 * species + 4), 0u};
+  uint32_t key[2] = {s->p.seed, s->p.run};
+  uint32_t r[4];
+  ora_philox4x32_10(ctr, key, r);
+  return r[slot & 3];
+}
 
 /* Box-Muller: two standard normals from two uniforms in (0, 1). */
 static void box_muller(double u1, double u2, double* a, double* b) {
@@ -628,7 +640,7 @@ int ora_step(ora_sim* s, int64_t nsteps) {
         /* (6) null-collision Monte Carlo */
         int child = 0;
         double cx = 0, cvx = 0, cvy = 0, cvz = 0;
-        if (alive && !(p->flags & F_NO_COLL) && u01(r0[1]) < s->pcoll[sp]) {
+        if (alive && !(p->flags & F_NO_COLL) && u01(candidacy_word(s, i, sp)) < s->pcoll[sp]) {
           double nu[3];
           if (sp == 0) {
             s->counters[C_E_CAND]++;

@@ -10,8 +10,9 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 PIC_OK, PIC_EINVAL, PIC_EHIP, PIC_ECAPACITY, PIC_EUNSTABLE, PIC_ETABLE, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6
 FLAG_NO_FIELD, FLAG_FIXED_E, FLAG_NO_COLL, FLAG_IMMOBILE_IONS, FLAG_RECORD, FLAG_THOMAS = 1, 2, 4, 8, 16, 32
 NCOUNTERS = 16
-NTIMERS = 4
-TIMER_NAMES = ["field", "electron", "ion", "sort"]
+NTIMERS = 10
+TIMER_NAMES = ["field", "electron", "ion", "sort", "e_decide", "e_emit", "e_rare", "i_decide",
+               "i_emit", "i_rare"]
 COUNTER_NAMES = [
     "steps", "e_pushed", "i_pushed", "e_absorbed", "e_reflected", "i_absorbed", "se_emitted",
     "e_candidates", "e_elastic", "e_excitation", "e_ionization", "i_candidates", "i_isotropic",
@@ -98,10 +99,12 @@ def load():
     L.pic_get_timing.argtypes = [P, P, P, ctypes.c_int]
     L.pic_selftest_philox.argtypes = [P, P, P, i64, P]
     L.pic_selftest_sqrt.argtypes = [P, P, i64, P]
+    L.pic_selftest_copy.argtypes = [P, P, i64, P]
     for name in ("pic_workspace_bytes", "pic_init", "pic_set_state", "pic_get_state", "pic_step",
                  "pic_sync", "pic_set_field", "pic_get_field", "pic_measure", "pic_moments",
                  "pic_get_counters", "pic_get_decisions", "pic_get_derived",
-                 "pic_selftest_philox", "pic_selftest_sqrt", "pic_timing", "pic_get_timing"):
+                 "pic_selftest_philox", "pic_selftest_sqrt", "pic_selftest_copy", "pic_timing",
+                 "pic_get_timing"):
         getattr(L, name).restype = ctypes.c_int
     _ = i32
     _lib = L

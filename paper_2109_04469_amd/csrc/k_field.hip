@@ -125,8 +125,6 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(FieldArgs a) {
   const int tid = threadIdx.x;
   const int nx = a.nx;
   if (tid == 0) {
-    a.ctl->ticket[0] = 0;
-    a.ctl->ticket[1] = 0;
     a.ctl->ncodes[1] = 0;
     a.ctl->counters[C_STEPS] += 1ull;
     if (a.measuring) a.ctl->msteps += 1;

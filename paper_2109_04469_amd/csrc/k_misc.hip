@@ -41,6 +41,25 @@ __global__ void k_selftest_sqrt(const double* in, double* out, int64_t n) {
   if (i < n) out[i] = sqrt(in[i]);
 }
 
+// Plain streaming copy, 16 bytes per lane per iteration: the reference
+// kernel for achievable HBM bandwidth and for scaling traffic counters.
+__global__ __launch_bounds__(256) void k_selftest_copy(const double2* __restrict__ in,
+                                                        double2* __restrict__ out, int64_t n2) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride)
+    out[i] = in[i];
+}
+
+hipError_t launch_selftest_copy(const double* in, double* out, int64_t n, hipStream_t s) {
+  const int64_t n2 = n / 2;
+  int64_t g = (n2 + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (g > 0)
+    hipLaunchKernelGGL(k_selftest_copy, dim3((unsigned)g), dim3(256), 0, s,
+                       reinterpret_cast<const double2*>(in), reinterpret_cast<double2*>(out), n2);
+  return hipGetLastError();
+}
+
 hipError_t launch_selftest_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                                   int64_t n, hipStream_t s) {
   const int64_t g = (n + 255) / 256;

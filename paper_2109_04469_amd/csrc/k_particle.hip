@@ -1,28 +1,31 @@
-// Particle kernel: one pass over a species' SoA streams per step, fusing
-// field gather, leap-frog push, the wall model and null-collision MCC with
-// order-preserving compaction, inline births and the CIC deposit of the new
-// positions (arXiv:2109.04469, Sec. 2 steps 3-6 and step 1 of the next step).
+// Particle pass of one species for one step: field gather, leap-frog push,
+// the wall model and null-collision MCC, with order-preserving compaction,
+// births and the CIC deposit of the new positions (arXiv:2109.04469, Sec. 2
+// steps 3-6 and step 1 of the next step).
 //
-// Schedule. A persistent grid (a few workgroups per CU) takes tiles of
-// kTile consecutive slots from an atomic ticket, so tiles are started in slot
-// order; the next ticket is requested while the current tile is processed.
-// Per tile:
-//   A  each thread loads kPPT particles (coalesced 8-byte streams), pushes
-//      them, applies the wall and decides the collision candidacy (and, for
-//      electrons, the process, which fixes the number of outputs); only the
-//      pushed state and a decision code stay in registers;
-//   B  a block scan of the per-particle output counts (0, 1 or 2 slots for
-//      the own species, 0 or 1 birth of the other species) and a decoupled
-//      look-back over earlier tiles (two lanes, one per count) give every
-//      output its global slot;
-//   C  outputs are written and the new positions deposited into an LDS
-//      histogram in 2^-32 fixed point. Particles that need collision
-//      kinematics, an ion process choice or a secondary electron (a small
-//      fraction) are handled afterwards in one non-unrolled loop, so the
-//      transcendental-heavy code exists once and does not set the register
-//      budget of the streaming part. The touched node range is then added to
-//      the global deposit with integer atomics (a few nodes per tile once the
-//      particles are cell-sorted) and cleared.
+// Two kernels per species step, with no dependency between workgroups inside
+// either of them:
+//   k_decide  streams x and vx, pushes, applies the wall and draws the
+//             collision candidacy (and for electrons the process, which fixes
+//             the number of outputs). The candidacy uniform of slot i is word
+//             i mod 4 of the block with counter (step, i / 4, 16 sp + 4, 0),
+//             so one block serves four slots; the wall and process uniforms
+//             come from the slot's own block (step, i, 16 sp, 0), drawn only
+//             for the few slots that need them. It writes a one-byte decision code per
+//             slot and the output, birth and queued-slot totals per tile of
+//             kTile slots,
+//             and deposits the new positions (and those of births) into LDS
+//             fixed-point histograms flushed with integer atomics.
+//   k_emit    takes a contiguous run of tiles per workgroup, forms its prefix
+//             from the per-tile totals, scans the codes inside each tile and
+//             writes every output to its compacted slot: it re-reads the
+//             particle and repeats the push bit for bit (same arithmetic, no
+//             contraction). Slots that need draws (collision kinematics, an
+//             ion process still to choose, a secondary electron) are queued
+//             with their output slots instead.
+//   k_rare    takes the queued slots, one per thread: a small fraction, kept
+//             out of the streaming kernels because their transcendental-heavy
+//             code would set those kernels' register budget.
 // Survivors keep their relative order and an ionization electron follows its
 // parent; births of the other species (Ar+ from ionization, secondary
 // electrons from ion impact) are appended after that species' particles in
@@ -31,65 +34,53 @@
 
 #include "pic_internal.h"
 
-#ifndef PIC_TICKETS
-#define PIC_TICKETS 1
-#endif
-#ifndef PIC_COOP
-#define PIC_COOP 0
-#endif
-#ifdef PIC_WAVES_PER_EU
-#define PIC_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(PIC_WAVES_PER_EU)))
-#else
-#define PIC_WAVES_ATTR
-#endif
-
 namespace pic {
 
-__device__ __forceinline__ uint64_t pack_status(uint32_t epoch, uint32_t flag, uint32_t value) {
-  return ((uint64_t)(epoch & 0x3FFFFFFFu) << 34) | ((uint64_t)flag << 32) | (uint64_t)value;
-}
+// Code bit used between the two kernels only: an Ar+ collision candidate
+// whose process (which needs a thermal atom velocity) is chosen in k_emit.
+// k_emit replaces it with the process bits, so a code read by the caller has
+// bit 6 clear.
+constexpr uint32_t kIonPending = 0x40u;
 
-// The wait on a predecessor is bounded: a tile is published by the
-// workgroup that took its ticket, which is already running, so the bound is
-// never reached in a correct run; if it were, the error is latched and the
-// kernel still ends.
-constexpr uint32_t kMaxSpin = 1u << 22;
+struct Outcome {
+  uint32_t own;    // output slots of this species: 0, 1 or 2
+  uint32_t birth;  // births of the other species: 0 or 1
+  bool rare;       // needs draws in k_emit
+};
 
-// Exclusive prefix of value `which` (0: own outputs, 1: births) over tiles
-// [0, t), from the status words of the earlier tiles.
-__device__ uint64_t look_back(uint64_t* tstat, int64_t t, int which, uint32_t epoch,
-                              DevCtl* ctl) {
-  uint64_t excl = 0;
-  int64_t pos = t - 1;
-  const uint64_t want = epoch & 0x3FFFFFFFu;
-  uint32_t spins = 0;
-  while (pos >= 0) {
-    const uint64_t w = ld_agent(tstat + 2 * pos + which);
-    const uint32_t flag = (uint32_t)(w >> 32) & 3u;
-    if ((w >> 34) != want || flag == 0) {
-      if (++spins >= kMaxSpin) {
-        latch_error(ctl, kErrLookback);
-        break;
-      }
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    excl += (uint32_t)w;
-    if (flag == 2) break;
-    --pos;
-  }
-  return excl;
-}
-
-// internal code bits beyond the recorded byte
-constexpr uint32_t kAlive = 1u << 8;
-constexpr uint32_t kPass = 1u << 9;
-constexpr uint32_t kIonCand = 1u << 10;  // ion collision candidate, process not yet chosen
-
+// What a decision code implies for the outputs. Slots carried without a
+// push (bit 7 clear) give one output.
 template <int SP>
-__device__ __forceinline__ bool is_rare(uint32_t c) {
-  if (SP == 0) return (c & kAlive) && ((c >> 3) & 7u) >= 2u;
-  return ((c & kAlive) && (c & kIonCand)) || (!(c & kAlive) && (c & 7u) == 3u && (c & kCodePushed));
+__device__ __forceinline__ Outcome outcome(uint32_t c) {
+  Outcome r{0u, 0u, false};
+  if (!(c & kCodePushed)) {
+    r.own = 1u;
+    return r;
+  }
+  const uint32_t wall = c & 7u;
+  const uint32_t proc = (c >> 3) & 7u;
+  if (SP == 0) {
+    const bool alive = wall == 0u || wall == 2u;
+    const bool ion = alive && proc == 4u;
+    r.own = alive ? (ion ? 2u : 1u) : 0u;
+    r.birth = ion ? 1u : 0u;
+    r.rare = alive && proc >= 2u;
+  } else {
+    const bool alive = wall == 0u;
+    r.own = alive ? 1u : 0u;
+    r.birth = wall == 3u ? 1u : 0u;
+    r.rare = (alive && (c & kIonPending)) || wall == 3u;
+  }
+  return r;
+}
+
+// Gather (linear interpolation in the particle's cell) and leap-frog push.
+// Both kernels call this on the same inputs and get the same bits.
+__device__ __forceinline__ void push(const double* E, int j, double f, double acc, double dts,
+                                     double& x, double& vx) {
+  const double Ep = (1.0 - f) * E[j] + f * E[j + 1];
+  vx = vx + acc * Ep;
+  x = x + vx * dts;
 }
 
 __device__ __forceinline__ void deposit_lds(unsigned long long* sH, double x, double inv_dx, int nx,
@@ -114,6 +105,297 @@ __device__ __forceinline__ void deposit_global(unsigned long long* dep, double x
   atomicAdd(&dep[j + 1], (unsigned long long)w1);
 }
 
+// Cumulative collision frequency of table `p` at table variable tv (speed /
+// table step), linear in tv; beyond the last table speed, the last entry.
+__device__ __forceinline__ double cum_nu(const double* cum, int ntab, int p, double tv) {
+  const double* c = cum + (int64_t)p * ntab;
+  if (tv < (double)(ntab - 1)) {
+    const int kk = (int)tv;
+    const double tt = tv - (double)kk;
+    return (1.0 - tt) * c[kk] + tt * c[kk + 1];
+  }
+  return c[ntab - 1];
+}
+
+// ---------------------------------------------------------------------------
+// k_decide
+
+template <int SP, bool MEASURE>
+__global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nx = a.nx;
+  double* sE = reinterpret_cast<double*>(smem);
+  unsigned long long* sH = reinterpret_cast<unsigned long long*>(sE + nx);
+  double* sEW = reinterpret_cast<double*>(sH + nx);                 // MEASURE
+  unsigned int* sEEPF = reinterpret_cast<unsigned int*>(sEW + nx);  // MEASURE
+
+  __shared__ uint32_t s_tot[3][kBlock / kWave];
+  __shared__ int s_lo, s_hi;
+  __shared__ unsigned long long s_cnt[NCOUNTERS];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  DevCtl* ctl = a.ctl;
+  const int par = a.parity;
+
+  for (int j = tid; j < nx; j += kBlock) {
+    sE[j] = a.E[j];
+    sH[j] = 0ull;
+    if (MEASURE) sEW[j] = 0.0;
+  }
+  if (MEASURE)
+    for (int b = tid; b < a.nbins; b += kBlock) sEEPF[b] = 0u;
+  if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
+  if (tid == 0) {
+    s_lo = INT_MAX;
+    s_hi = -1;
+  }
+
+  // slots [0, n_push) are pushed; [n_push, n_tot) were born earlier in this
+  // step (ions from this step's electron pass) and are carried unchanged
+  int64_t n_push = uniform64(SP == 0 ? ctl->n_e[par] : ctl->n_i[par]);
+  int64_t n_tot = SP == 0 ? n_push : n_push + uniform64(ctl->i_births);
+  if (n_tot > a.cap) {
+    if (tid == 0 && blockIdx.x == 0) latch_error(ctl, kErrCapacity);
+    n_tot = a.cap;
+    if (n_push > n_tot) n_push = n_tot;
+  }
+  const int ntiles = uniform32((int)((n_tot + kTile - 1) / kTile));
+
+  if (blockIdx.x == 0 && tid == 0) {
+    if (a.record) ctl->ncodes[SP] = n_push;
+    atomicAdd(&ctl->counters[SP == 0 ? C_E_PUSHED : C_I_PUSHED], (unsigned long long)n_push);
+  }
+  __syncthreads();
+
+  const uint32_t step = a.step;
+  const double inv_dx = a.inv_dx;
+  const double L = a.L;
+
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t base = (int64_t)t * kTile;
+    uint32_t own = 0, births = 0, rares = 0;
+    int jlo = INT_MAX, jhi = -1;
+    // each thread takes runs of four consecutive slots (16-byte loads, one
+    // Philox block for the four candidacy draws, one 4-byte code store)
+#pragma unroll
+    for (int g = 0; g < kPPT / 4; ++g) {
+      const int64_t s0 = base + (int64_t)g * (4 * kBlock) + 4 * tid;
+      if (s0 >= n_tot) continue;
+      const bool full = s0 + 3 < n_tot;
+      double xs[4], vxs[4];
+      if (full) {
+        const double2* xp = reinterpret_cast<const double2*>(a.xin + s0);
+        const double2* vp = reinterpret_cast<const double2*>(a.vxin + s0);
+        const double2 x01 = xp[0], x23 = xp[1], v01 = vp[0], v23 = vp[1];
+        xs[0] = x01.x, xs[1] = x01.y, xs[2] = x23.x, xs[3] = x23.y;
+        vxs[0] = v01.x, vxs[1] = v01.y, vxs[2] = v23.x, vxs[3] = v23.y;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          xs[q] = s0 + q < n_tot ? a.xin[s0 + q] : 0.0;
+          vxs[q] = s0 + q < n_tot ? a.vxin[s0 + q] : 0.0;
+        }
+      }
+      uint4 rc = make_uint4(0u, 0u, 0u, 0u);
+      if (s0 < n_push) rc = draw(step, (uint32_t)(s0 >> 2), SP, 4, a.seed, a.run);
+      const uint32_t ucs[4] = {rc.x, rc.y, rc.z, rc.w};
+      uint32_t codes4 = 0;
+      // deposit of this run of slots, combined while they share a cell
+      int jr = -1;
+      unsigned long long h0 = 0, h1 = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t slot = s0 + q;
+        if (slot >= n_tot) break;
+        double x = xs[q], vx = vxs[q];
+        uint32_t c = 0, o = 1, b = 0, mul = 1;
+        if (slot < n_push) {
+          c = kCodePushed;
+          int j;
+          double f;
+          int64_t w1;
+          cell_of(x, inv_dx, nx, j, f, w1);
+          double vy = 0.0, vz = 0.0;
+          if (MEASURE) {
+            vy = a.vyin[slot];
+            vz = a.vzin[slot];
+            const double eps = a.ek * (vx * vx + vy * vy + vz * vz);
+            atomicAdd(&sEW[j], ((double)(kOne32 - w1) * kInvTwo32) * eps);
+            atomicAdd(&sEW[j + 1], ((double)w1 * kInvTwo32) * eps);
+            jlo = min(jlo, j);
+            jhi = max(jhi, j + 1);
+            if (fabs(x - a.half) <= a.eepf_hw) {
+              const int64_t bin = (int64_t)(eps * a.inv_de);
+              if (bin >= 0 && bin < a.nbins) atomicAdd(&sEEPF[bin], 1u);
+            }
+          }
+          push(sE, j, f, a.acc, a.dts, x, vx);
+          bool alive = true;
+          if (!isfinite(x) || !isfinite(vx)) {
+            latch_error(ctl, kErrUnstable);
+            alive = false;
+            c |= 1u;
+          } else if (x < 0.0 || x > L) {
+            const double ub = u01(draw(step, (uint32_t)slot, SP, 0, a.seed, a.run).x);
+            if (SP == 0) {
+              if (ub < a.p_wall) {
+                x = (x < 0.0) ? -x : (L + L) - x;
+                vx = -vx;
+                if (x < 0.0 || x > L) {
+                  alive = false;
+                  c |= 4u;
+                  atomicAdd(&s_cnt[C_REFLECT_LOST], 1ull);
+                } else {
+                  c |= 2u;
+                  atomicAdd(&s_cnt[C_E_REFLECTED], 1ull);
+                }
+              } else {
+                alive = false;
+                c |= 1u;
+                atomicAdd(&s_cnt[C_E_ABSORBED], 1ull);
+              }
+            } else {
+              alive = false;
+              atomicAdd(&s_cnt[C_I_ABSORBED], 1ull);
+              if (ub < a.p_wall) {
+                // a secondary electron leaves the wall the ion hit
+                c |= 3u;
+                b = 1;
+                atomicAdd(&s_cnt[C_SE_EMITTED], 1ull);
+                deposit_global(a.dep_other, x < 0.0 ? 0.0 : L, inv_dx, nx);
+              } else {
+                c |= 1u;
+              }
+            }
+          }
+          if (alive && !a.no_coll && u01(ucs[q]) < a.pcoll) {
+            if (SP == 0) {
+              // electron candidate: the process at this speed decides
+              // whether a second electron and an ion are born
+              atomicAdd(&s_cnt[C_E_CAND], 1ull);
+              if (!MEASURE) {
+                vy = a.vyin[slot];
+                vz = a.vzin[slot];
+              }
+              const double g2 = sqrt(vx * vx + vy * vy + vz * vz);
+              const double tv = g2 * a.inv_dv;
+              const double r = u01(draw(step, (uint32_t)slot, SP, 0, a.seed, a.run).z) * a.numax;
+              if (!(tv < (double)(a.ntab - 1))) atomicAdd(&s_cnt[C_BEYOND_TABLE], 1ull);
+              uint32_t proc = 1;
+              if (r < cum_nu(a.cum, a.ntab, 0, tv)) {
+                proc = 2;
+                atomicAdd(&s_cnt[C_E_ELASTIC], 1ull);
+              } else if (r < cum_nu(a.cum, a.ntab, 1, tv)) {
+                proc = 3;
+                atomicAdd(&s_cnt[C_E_EXC], 1ull);
+              } else if (r < cum_nu(a.cum, a.ntab, 2, tv)) {
+                proc = 4;
+                b = 1;
+                mul = 2;
+                atomicAdd(&s_cnt[C_E_ION], 1ull);
+                deposit_global(a.dep_other, x, inv_dx, nx);
+              }
+              c |= proc << 3;
+            } else {
+              atomicAdd(&s_cnt[C_I_CAND], 1ull);
+              c |= kIonPending;
+            }
+          }
+          o = alive ? mul : 0u;
+        }
+        if (o) {
+          // an ionization electron is born at its parent's position
+          int j;
+          double f;
+          int64_t w1;
+          cell_of(x, inv_dx, nx, j, f, w1);
+          if (j != jr) {
+            if (jr >= 0) {
+              atomicAdd(&sH[jr], h0);
+              atomicAdd(&sH[jr + 1], h1);
+            }
+            jr = j;
+            h0 = h1 = 0ull;
+            jlo = min(jlo, j);
+            jhi = max(jhi, j + 1);
+          }
+          h0 += (unsigned long long)o * (unsigned long long)(kOne32 - w1);
+          h1 += (unsigned long long)o * (unsigned long long)w1;
+        }
+        codes4 |= c << (8 * q);
+        own += o;
+        births += b;
+        rares += outcome<SP>(c).rare ? 1u : 0u;
+      }
+      if (jr >= 0) {
+        atomicAdd(&sH[jr], h0);
+        atomicAdd(&sH[jr + 1], h1);
+      }
+      if (full) {
+        *reinterpret_cast<uint32_t*>(a.codes + s0) = codes4;
+      } else {
+        for (int q = 0; q < 4 && s0 + q < n_tot; ++q) a.codes[s0 + q] = (uint8_t)(codes4 >> (8 * q));
+      }
+    }
+
+    // tile totals and the touched deposit range
+    own = wave_sum<unsigned int>(own);
+    births = wave_sum<unsigned int>(births);
+    rares = wave_sum<unsigned int>(rares);
+    jlo = wave_min(jlo);
+    jhi = wave_max(jhi);
+    if (lane == 0) {
+      s_tot[0][wave] = own;
+      s_tot[1][wave] = births;
+      s_tot[2][wave] = rares;
+      atomicMin(&s_lo, jlo);
+      atomicMax(&s_hi, jhi);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t o = 0, b = 0, r = 0;
+      for (int w = 0; w < kBlock / kWave; ++w) {
+        o += s_tot[0][w];
+        b += s_tot[1][w];
+        r += s_tot[2][w];
+      }
+      a.tcnt[t] = o | (b << 16) | (r << 32);
+    }
+    const int lo = s_lo, hi = s_hi;  // lo > hi when the tile deposited nothing
+    for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += kBlock) {
+      const unsigned long long v = sH[j];
+      if (v) {
+        atomicAdd(&a.dep_own[j], v);
+        sH[j] = 0ull;
+      }
+      if (MEASURE) {
+        const double e = sEW[j];
+        if (e != 0.0) {
+          atomicAdd(&a.acc_ew[j], e);
+          sEW[j] = 0.0;
+        }
+      }
+    }
+    __syncthreads();  // s_lo, s_hi and s_tot have been read
+    if (tid == 0) {
+      s_lo = INT_MAX;
+      s_hi = -1;
+    }
+    __syncthreads();
+  }
+
+  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
+  if (MEASURE) {
+    for (int b = tid; b < a.nbins; b += kBlock)
+      if (sEEPF[b]) atomicAdd(&a.eepf[b], (unsigned long long)sEEPF[b]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_emit
+
 __device__ __forceinline__ void store4(const PartArgs& a, int64_t i, double x, double vx, double vy,
                                        double vz) {
   a.xout[i] = x;
@@ -122,18 +404,214 @@ __device__ __forceinline__ void store4(const PartArgs& a, int64_t i, double x, d
   a.vzout[i] = vz;
 }
 
-// Collision kinematics, the ion process choice and secondary emission for
-// one particle, then its outputs and deposit. Kept out of line: it runs for a
-// small fraction of particles and its transcendental-heavy code would
-// otherwise set the register budget of the whole streaming pass.
+// k_decide's push and reflection, repeated on the slot's input state.
+__device__ __forceinline__ void repush(const PartArgs& a, const double* E, uint32_t c, double& x,
+                                       double& vx) {
+  if (c & kCodePushed) {
+    int j;
+    double f;
+    int64_t w1;
+    cell_of(x, a.inv_dx, a.nx, j, f, w1);
+    push(E, j, f, a.acc, a.dts, x, vx);
+    if ((c & 7u) == 2u) {
+      x = (x < 0.0) ? -x : (a.L + a.L) - x;
+      vx = -vx;
+    }
+  }
+}
+
+__device__ __forceinline__ void reload(const PartArgs& a, const double* E, int64_t slot,
+                                       uint32_t c, double& x, double& vx, double& vy, double& vz) {
+  x = a.xin[slot];
+  vx = a.vxin[slot];
+  vy = a.vyin[slot];
+  vz = a.vzin[slot];
+  repush(a, E, c, x, vx);
+}
+
+// slots per thread whose loads are in flight together
+#ifndef EMIT_GROUP
+#define EMIT_GROUP 4
+#endif
+constexpr int kEmitGroup = EMIT_GROUP;
+
 template <int SP>
-__device__ __forceinline__ void rare_particle(const PartArgs& a, unsigned long long* sH,
-                                           unsigned long long* s_cnt, int64_t slot, uint32_t c,
-                                           double x, double vx, double vy, double vz,
-                                           int64_t dest, int64_t bdest, int& jlo, int& jhi) {
+__global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sE = reinterpret_cast<double*>(smem);
+  __shared__ uint32_t s_wtot[kPPT][kBlock / kWave];
+  __shared__ uint32_t s_woff[kPPT][kBlock / kWave];
+  __shared__ uint64_t s_red[3][kBlock / kWave];
+  __shared__ uint32_t s_agg, s_qn;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  DevCtl* ctl = a.ctl;
+  const int par = a.parity;
+
+  int64_t n_push = uniform64(SP == 0 ? ctl->n_e[par] : ctl->n_i[par]);
+  int64_t n_tot = SP == 0 ? n_push : n_push + uniform64(ctl->i_births);
+  if (n_tot > a.cap) n_tot = a.cap;  // k_decide has latched the error
+  const int64_t bbase = uniform64(SP == 0 ? ctl->n_i[par] : ctl->e_out);
+  const int ntiles = uniform32((int)((n_tot + kTile - 1) / kTile));
+
+  if (ntiles == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
+      ctl->n_rare[SP] = 0;
+      if (SP == 0) {
+        ctl->e_out = 0;
+        ctl->n_e[par ^ 1] = 0;
+        ctl->i_births = 0;
+        ctl->n_i[par ^ 1] = ctl->n_i[par];
+      } else {
+        ctl->n_i[par ^ 1] = 0;
+        ctl->n_e[par ^ 1] = ctl->e_out;
+      }
+    }
+    return;
+  }
+  // this workgroup's contiguous run of tiles
+  const int t0 = uniform32((int)((int64_t)ntiles * blockIdx.x / gridDim.x));
+  const int t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
+  if (t0 >= t1) return;
+
+  for (int j = tid; j < a.nx; j += kBlock) sE[j] = a.E[j];
+  if (tid == 0) s_qn = 0;
+  // outputs, births and queued slots of all earlier tiles
+  unsigned long long po = 0, pb = 0, pr = 0;
+  for (int t = tid; t < t0; t += kBlock) {
+    const uint64_t v = a.tcnt[t];
+    po += v & 0xFFFFull;
+    pb += (v >> 16) & 0xFFFFull;
+    pr += v >> 32;
+  }
+  po = wave_sum<unsigned long long>(po);
+  pb = wave_sum<unsigned long long>(pb);
+  pr = wave_sum<unsigned long long>(pr);
+  if (lane == 0) {
+    s_red[0][wave] = po;
+    s_red[1][wave] = pb;
+    s_red[2][wave] = pr;
+  }
+  __syncthreads();
+  int64_t prefO = 0, prefB = 0, prefR = 0;
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    prefO += (int64_t)s_red[0][w];
+    prefB += (int64_t)s_red[1][w];
+    prefR += (int64_t)s_red[2][w];
+  }
+
+  for (int t = t0; t < t1; ++t) {
+    const int64_t base = (int64_t)t * kTile;
+    uint32_t code[kPPT], loc[kPPT];
+#pragma unroll
+    for (int k = 0; k < kPPT; ++k) {
+      const int64_t slot = base + k * kBlock + tid;
+      uint32_t c = 0, cnt = 0;
+      if (slot < n_tot) {
+        c = a.codes[slot];
+        const Outcome oc = outcome<SP>(c);
+        cnt = oc.own | (oc.birth << 16);
+        c |= 0x100u;  // slot in range
+      }
+      code[k] = c;
+      const uint32_t inc = wave_incl_scan<unsigned int>(cnt);
+      loc[k] = inc - cnt;
+      if (lane == kWave - 1) s_wtot[k][wave] = inc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t run = 0;
+      for (int k = 0; k < kPPT; ++k)
+        for (int w = 0; w < kBlock / kWave; ++w) {
+          s_woff[k][w] = run;
+          run += s_wtot[k][w];
+        }
+      s_agg = run;
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int g = 0; g < kPPT; g += kEmitGroup) {
+      double px[kEmitGroup], pvx[kEmitGroup], pvy[kEmitGroup], pvz[kEmitGroup];
+#pragma unroll
+      for (int q = 0; q < kEmitGroup; ++q) {
+        const int64_t slot = base + (g + q) * kBlock + tid;
+        px[q] = pvx[q] = pvy[q] = pvz[q] = 0.0;
+        if (code[g + q] & 0x100u) {
+          px[q] = a.xin[slot];
+          pvx[q] = a.vxin[slot];
+          pvy[q] = a.vyin[slot];
+          pvz[q] = a.vzin[slot];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kEmitGroup; ++q) {
+        const int k = g + q;
+        const uint32_t c = code[k];
+        const Outcome oc = outcome<SP>(c);
+        const bool in = (c & 0x100u) != 0;
+        const uint32_t off = s_woff[k][wave] + loc[k];
+        const bool rare = in && oc.rare;
+        const uint64_t m = __ballot(rare);
+        if (m) {
+          // queue the slot for k_rare with its output slots
+          uint32_t qb = 0;
+          if (lane == 0) qb = atomicAdd(&s_qn, (uint32_t)__popcll(m));
+          qb = __shfl(qb, 0);
+          if (rare) {
+            const int64_t pos = prefR + qb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            a.rq[pos] = make_uint4((uint32_t)(base + k * kBlock + tid), c & 0xFFu,
+                                   (uint32_t)(prefO + (off & 0xFFFFu)),
+                                   (uint32_t)(bbase + prefB + (off >> 16)));
+          }
+        }
+        if (!in || rare || !oc.own) continue;
+        const int64_t dest = prefO + (int64_t)(off & 0xFFFFu);
+        double x = px[q], vx = pvx[q];
+        repush(a, sE, c, x, vx);
+        if (dest < a.cap) store4(a, dest, x, vx, pvy[q], pvz[q]);
+      }
+    }
+    __syncthreads();
+    const uint32_t agg = s_agg;
+    prefO += agg & 0xFFFFu;
+    prefB += agg >> 16;
+    prefR += s_qn;
+    if (t == ntiles - 1 && tid == 0) {
+      ctl->n_rare[SP] = prefR;
+      if (SP == 0) {
+        ctl->e_out = prefO;
+        ctl->n_e[par ^ 1] = prefO;
+        ctl->i_births = prefB;
+        ctl->n_i[par ^ 1] = bbase + prefB;
+      } else {
+        ctl->n_i[par ^ 1] = prefO;
+        ctl->n_e[par ^ 1] = bbase + prefB;
+      }
+      if (prefO > a.cap || bbase + prefB > a.bcap) latch_error(ctl, kErrCapacity);
+    }
+    __syncthreads();  // s_woff, s_agg and s_qn are reused by the next tile
+    if (tid == 0) s_qn = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_rare: the queued slots, one per thread
+
+// Collision kinematics, the ion process choice and secondary emission for
+// one slot, and its outputs at dest (own species) and bdest (births). E is
+// read from global memory here (the same values k_decide used).
+template <int SP>
+__device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long* s_cnt,
+                          int64_t slot, uint32_t c, int64_t dest, int64_t bdest) {
   const uint32_t step = a.step;
   const double L = a.L;
-  bool child = false, birth = false;
+  double x, vx, vy, vz;
+  reload(a, a.E, slot, c, x, vx, vy, vz);
+  const Outcome oc = outcome<SP>(c);
+  bool child = false;
   double cvx = 0, cvy = 0, cvz = 0, bxp = 0, bvx = 0, bvy = 0, bvz = 0;
   if (SP == 0) {
     const uint32_t proc = (c >> 3) & 7u;
@@ -182,13 +660,12 @@ __device__ __forceinline__ void rare_particle(const PartArgs& a, unsigned long l
       double n1, n2, n3, dmy;
       box_muller(u01(r3.x), u01(r3.y), n1, n2);
       box_muller(u01(r3.z), u01(r3.w), n3, dmy);
-      birth = true;
       bxp = x;
       bvx = a.sig_g * n1;
       bvy = a.sig_g * n2;
       bvz = a.sig_g * n3;
     }
-  } else if (c & kAlive) {
+  } else if (oc.own) {
     // Ar+ candidate on a thermal atom drawn for it: isotropic elastic in the
     // CM frame, backward (charge transfer), or null
     const uint4 r0 = draw(step, (uint32_t)slot, 1, 0, a.seed, a.run);
@@ -200,22 +677,10 @@ __device__ __forceinline__ void rare_particle(const PartArgs& a, unsigned long l
     const double gx = vx - ax, gy = vy - ay, gz = vz - az;
     const double g = sqrt(gx * gx + gy * gy + gz * gz);
     const double tv = g * a.inv_dv;
-    const double* c0 = a.cum;
-    const double* c1 = a.cum + a.ntab;
-    double nu0, nu1;
-    if (tv < (double)(a.ntab - 1)) {
-      const int kk = (int)tv;
-      const double tt = tv - (double)kk;
-      nu0 = (1.0 - tt) * c0[kk] + tt * c0[kk + 1];
-      nu1 = (1.0 - tt) * c1[kk] + tt * c1[kk + 1];
-    } else {
-      atomicAdd(&s_cnt[C_BEYOND_TABLE], 1ull);
-      nu0 = c0[a.ntab - 1];
-      nu1 = c1[a.ntab - 1];
-    }
+    if (!(tv < (double)(a.ntab - 1))) atomicAdd(&s_cnt[C_BEYOND_TABLE], 1ull);
     const double r = u01(r0.z) * a.numax;
     uint32_t proc = 1;
-    if (r < nu0) {
+    if (r < cum_nu(a.cum, a.ntab, 0, tv)) {
       proc = 2;
       atomicAdd(&s_cnt[C_I_ISO], 1ull);
       const uint4 r2 = draw(step, (uint32_t)slot, 1, 2, a.seed, a.run);
@@ -225,429 +690,123 @@ __device__ __forceinline__ void rare_particle(const PartArgs& a, unsigned long l
       vx = 0.5 * (vx + ax) + hg * ux;
       vy = 0.5 * (vy + ay) + hg * uy;
       vz = 0.5 * (vz + az) + hg * uz;
-    } else if (r < nu1) {
+    } else if (r < cum_nu(a.cum, a.ntab, 1, tv)) {
       proc = 3;
       atomicAdd(&s_cnt[C_I_BACK], 1ull);
       vx = ax;
       vy = ay;
       vz = az;
     }
-    c |= proc << 3;
-    if (a.record) a.codes[slot] = (uint8_t)(c & 0xFFu);
+    a.codes[slot] = (uint8_t)((c & ~kIonPending) | (proc << 3));
   } else {
     // secondary electron from the wall the ion hit, half-Maxwellian
     const uint4 r3 = draw(step, (uint32_t)slot, 1, 3, a.seed, a.run);
     double n1, n2, n3, dmy;
     box_muller(u01(r3.x), u01(r3.y), n1, n2);
     box_muller(u01(r3.z), u01(r3.w), n3, dmy);
-    birth = true;
     bxp = (x < 0.0) ? 0.0 : L;
     bvx = a.sig_se * fabs(n1);
     if (x > L) bvx = -bvx;
     bvy = a.sig_se * n2;
     bvz = a.sig_se * n3;
   }
-  if (c & kAlive) {
+  if (oc.own) {
     if (dest < a.cap) store4(a, dest, x, vx, vy, vz);
     if (child && dest + 1 < a.cap) store4(a, dest + 1, x, cvx, cvy, cvz);
-    deposit_lds(sH, x, a.inv_dx, a.nx, child ? 2ull : 1ull, jlo, jhi);
   }
-  if (birth) {
-    if (bdest < a.bcap) {
-      a.bx[bdest] = bxp;
-      a.bvx[bdest] = bvx;
-      a.bvy[bdest] = bvy;
-      a.bvz[bdest] = bvz;
-    }
-    deposit_global(a.dep_other, bxp, a.inv_dx, a.nx);
+  if (oc.birth && bdest < a.bcap) {
+    a.bx[bdest] = bxp;
+    a.bvx[bdest] = bvx;
+    a.bvy[bdest] = bvy;
+    a.bvz[bdest] = bvz;
   }
 }
 
-template <int SP, bool MEASURE>
-__global__ __launch_bounds__(kBlock) PIC_WAVES_ATTR void k_particle(PartArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int nx = a.nx;
-  double* sE = reinterpret_cast<double*>(smem);
-  unsigned long long* sH = reinterpret_cast<unsigned long long*>(sE + nx);
-  double* sEW = reinterpret_cast<double*>(sH + nx);                 // MEASURE
-  unsigned int* sEEPF = reinterpret_cast<unsigned int*>(sEW + nx);  // MEASURE
-
-  __shared__ uint32_t s_wtot[kPPT][kBlock / kWave];
-  __shared__ uint32_t s_woff[kPPT][kBlock / kWave];
-  __shared__ uint32_t s_agg[2];
-  __shared__ int s_tile;
-  __shared__ uint64_t s_pref[2];
-  __shared__ int s_lo, s_hi;
+template <int SP>
+__global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
   __shared__ unsigned long long s_cnt[NCOUNTERS];
-
   const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wave = tid / kWave;
-  DevCtl* ctl = a.ctl;
-  const int par = a.parity;
-
-  for (int j = tid; j < nx; j += kBlock) {
-    sE[j] = a.E[j];
-    sH[j] = 0ull;
-    if (MEASURE) sEW[j] = 0.0;
-  }
-  if (MEASURE)
-    for (int b = tid; b < a.nbins; b += kBlock) sEEPF[b] = 0u;
   if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
-  if (tid == 0) {
-    s_lo = INT_MAX;
-    s_hi = -1;
-  }
-
-  // counts beyond the buffers only arise after a capacity error, which is
-  // latched; clamp so no access leaves the arrays
-  int64_t n_push = uniform64(SP == 0 ? ctl->n_e[par] : ctl->n_i[par]);
-  int64_t n_tot = SP == 0 ? n_push : n_push + uniform64(ctl->i_births);
-  if (n_tot > a.cap) {
-    if (tid == 0) latch_error(ctl, kErrCapacity);
-    n_tot = a.cap;
-    if (n_push > n_tot) n_push = n_tot;
-  }
-  const int64_t bbase = uniform64(SP == 0 ? ctl->n_i[par] : ctl->e_out);
-  const int ntiles = uniform32((int)((n_tot + kTile - 1) / kTile));
-
-  if (blockIdx.x == 0 && tid == 0) {
-    if (a.record) ctl->ncodes[SP] = n_push;
-    atomicAdd(&ctl->counters[SP == 0 ? C_E_PUSHED : C_I_PUSHED], (unsigned long long)n_push);
-    if (ntiles == 0) {
-      if (SP == 0) {
-        ctl->e_out = 0;
-        ctl->n_e[par ^ 1] = 0;
-        ctl->i_births = 0;
-        ctl->n_i[par ^ 1] = ctl->n_i[par];
-      } else {
-        ctl->n_i[par ^ 1] = 0;
-        ctl->n_e[par ^ 1] = ctl->e_out;
-      }
-    }
-  }
-
-  const uint32_t step = a.step;
-  const double inv_dx = a.inv_dx;
-  const double L = a.L;
-
-  // The ticket is fetched by one thread in the middle of the loop body, never
-  // at the loop header: with a divergent region at the header the compiler
-  // may rotate the loop so that only the fetching lane goes round through the
-  // fetch while the others re-enter at the barrier and re-read a stale tile.
-#if PIC_TICKETS
-  if (tid == 0) s_tile = (int)atomicAdd(&ctl->ticket[SP], 1u);
   __syncthreads();
-  int t = uniform32(s_tile);
-#else
-  int t = (int)blockIdx.x;
-#endif
-  while (t < ntiles) {
-    const int64_t base = (int64_t)t * kTile;
-#if PIC_TICKETS
-    // the next ticket is requested now; its latency hides behind this tile
-    uint32_t next_ticket = 0;
-    if (tid == 0) next_ticket = atomicAdd(&ctl->ticket[SP], 1u);
-#endif
-
-    // ---------------- phase A: push, wall, collision decision -------------
-    double px[kPPT], pvx[kPPT], pvy[kPPT], pvz[kPPT];
-    uint32_t code[kPPT], cnt[kPPT];
-    int jlo = INT_MAX, jhi = -1;
-#pragma unroll
-    for (int k = 0; k < kPPT; ++k) {
-      const int64_t slot = base + k * kBlock + tid;
-      uint32_t c = 0, o = 0, b = 0;
-      double x = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
-      if (slot < n_tot) {
-        x = a.xin[slot];
-        vx = a.vxin[slot];
-        vy = a.vyin[slot];
-        vz = a.vzin[slot];
-        if (slot >= n_push) {
-          c = kPass;  // born earlier this step: carried, not pushed
-          o = 1;
-        } else {
-          c = kCodePushed;
-          int j;
-          double f;
-          int64_t w1;
-          cell_of(x, inv_dx, nx, j, f, w1);
-          if (MEASURE) {
-            const double eps = a.ek * (vx * vx + vy * vy + vz * vz);
-            atomicAdd(&sEW[j], ((double)(kOne32 - w1) * kInvTwo32) * eps);
-            atomicAdd(&sEW[j + 1], ((double)w1 * kInvTwo32) * eps);
-            jlo = min(jlo, j);
-            jhi = max(jhi, j + 1);
-            if (fabs(x - a.half) <= a.eepf_hw) {
-              const int64_t bin = (int64_t)(eps * a.inv_de);
-              if (bin >= 0 && bin < a.nbins) atomicAdd(&sEEPF[bin], 1u);
-            }
-          }
-          // gather (linear interpolation) and leap-frog push
-          const double Ep = (1.0 - f) * sE[j] + f * sE[j + 1];
-          vx = vx + a.acc * Ep;
-          x = x + vx * a.dts;
-          const uint4 r0 = draw(step, (uint32_t)slot, SP, 0, a.seed, a.run);
-          bool alive = true;
-          if (!isfinite(x) || !isfinite(vx)) {
-            latch_error(ctl, kErrUnstable);
-            alive = false;
-            c |= 1u;
-          } else if (x < 0.0 || x > L) {
-            const double ub = u01(r0.x);
-            if (SP == 0) {
-              if (ub < a.p_wall) {
-                x = (x < 0.0) ? -x : (L + L) - x;
-                vx = -vx;
-                if (x < 0.0 || x > L) {
-                  alive = false;
-                  c |= 4u;
-                  atomicAdd(&s_cnt[C_REFLECT_LOST], 1ull);
-                } else {
-                  c |= 2u;
-                  atomicAdd(&s_cnt[C_E_REFLECTED], 1ull);
-                }
-              } else {
-                alive = false;
-                c |= 1u;
-                atomicAdd(&s_cnt[C_E_ABSORBED], 1ull);
-              }
-            } else {
-              alive = false;
-              atomicAdd(&s_cnt[C_I_ABSORBED], 1ull);
-              if (ub < a.p_wall) {
-                c |= 3u;
-                b = 1;
-                atomicAdd(&s_cnt[C_SE_EMITTED], 1ull);
-              } else {
-                c |= 1u;
-              }
-            }
-          }
-          if (alive && !a.no_coll && u01(r0.y) < a.pcoll) {
-            if (SP == 0) {
-              // electron candidate: the process at this speed (it decides
-              // whether a second electron and an ion are born)
-              atomicAdd(&s_cnt[C_E_CAND], 1ull);
-              const double g = sqrt(vx * vx + vy * vy + vz * vz);
-              const double tv = g * a.inv_dv;
-              const double r = u01(r0.z) * a.numax;
-              const double* c0 = a.cum;
-              const double* c1 = a.cum + a.ntab;
-              const double* c2 = a.cum + 2 * a.ntab;
-              int kk = a.ntab - 1;
-              double tt = 0.0;
-              const bool inside = tv < (double)(a.ntab - 1);
-              double nu0, nu1;
-              if (inside) {
-                kk = (int)tv;
-                tt = tv - (double)kk;
-                nu0 = (1.0 - tt) * c0[kk] + tt * c0[kk + 1];
-                nu1 = (1.0 - tt) * c1[kk] + tt * c1[kk + 1];
-              } else {
-                // beyond the last table speed: its entry (still <= nu_max)
-                atomicAdd(&s_cnt[C_BEYOND_TABLE], 1ull);
-                nu0 = c0[kk];
-                nu1 = c1[kk];
-              }
-              uint32_t proc = 1;
-              if (r < nu0) {
-                proc = 2;
-                atomicAdd(&s_cnt[C_E_ELASTIC], 1ull);
-              } else if (r < nu1) {
-                proc = 3;
-                atomicAdd(&s_cnt[C_E_EXC], 1ull);
-              } else {
-                const double nu2 = inside ? (1.0 - tt) * c2[kk] + tt * c2[kk + 1] : c2[kk];
-                if (r < nu2) {
-                  proc = 4;
-                  b = 1;
-                  atomicAdd(&s_cnt[C_E_ION], 1ull);
-                }
-              }
-              c |= proc << 3;
-            } else {
-              // ion candidate: the process needs a thermal atom velocity and
-              // does not change the number of outputs; chosen in the rare pass
-              atomicAdd(&s_cnt[C_I_CAND], 1ull);
-              c |= kIonCand;
-            }
-          }
-          if (alive) {
-            c |= kAlive;
-            o = 1 + ((SP == 0 && ((c >> 3) & 7u) == 4u) ? 1 : 0);
-          }
-          if (a.record && !(SP == 1 && (c & kIonCand))) a.codes[slot] = (uint8_t)(c & 0xFFu);
-        }
-      }
-      px[k] = x;
-      pvx[k] = vx;
-      pvy[k] = vy;
-      pvz[k] = vz;
-      code[k] = c;
-      cnt[k] = o | (b << 16);
-    }
-
-    // ---------------- phase B: tile scan and decoupled look-back ----------
-    uint32_t loc[kPPT];
-#pragma unroll
-    for (int k = 0; k < kPPT; ++k) {
-      const uint32_t inc = wave_incl_scan<unsigned int>(cnt[k]);
-      loc[k] = inc - cnt[k];
-      if (lane == kWave - 1) s_wtot[k][wave] = inc;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      uint32_t run = 0;
-      for (int k = 0; k < kPPT; ++k)
-        for (int w = 0; w < kBlock / kWave; ++w) {
-          s_woff[k][w] = run;
-          run += s_wtot[k][w];
-        }
-      s_agg[0] = run & 0xFFFFu;
-      s_agg[1] = run >> 16;
-    }
-    __syncthreads();
-    if (tid < 2) {
-      // lane 0: own outputs, lane 1: births of the other species
-      const uint32_t agg = s_agg[tid];
-      uint64_t* st = a.tstat + 2 * (int64_t)t + tid;
-      uint64_t pre = 0;
-      if (t == 0) {
-        st_agent(st, pack_status(a.epoch, 2, agg));
-      } else {
-        st_agent(st, pack_status(a.epoch, 1, agg));
-        pre = look_back(a.tstat, t, tid, a.epoch, ctl);
-        st_agent(st, pack_status(a.epoch, 2, (uint32_t)(pre + agg)));
-      }
-      s_pref[tid] = pre;
-    }
-    __syncthreads();
-    const int64_t prefO = (int64_t)s_pref[0];
-    const int64_t prefB = (int64_t)s_pref[1];
-    if (tid == 0 && t == ntiles - 1) {
-      const int64_t totO = prefO + (int64_t)s_agg[0], totB = prefB + (int64_t)s_agg[1];
-      if (SP == 0) {
-        ctl->e_out = totO;
-        ctl->n_e[par ^ 1] = totO;
-        ctl->i_births = totB;
-        ctl->n_i[par ^ 1] = bbase + totB;
-      } else {
-        ctl->n_i[par ^ 1] = totO;
-        ctl->n_e[par ^ 1] = bbase + totB;
-      }
-      if (totO > a.cap || bbase + totB > a.bcap) latch_error(ctl, kErrCapacity);
-    }
-
-    // ---------------- phase C: write and deposit ----------------------------
-    bool any_rare = false;
-#pragma unroll
-    for (int k = 0; k < kPPT; ++k) {
-      const uint32_t c = code[k];
-      if (is_rare<SP>(c)) {
-        any_rare = true;
-        continue;
-      }
-      if (!((c & kAlive) || (c & kPass))) continue;
-      const int64_t dest = prefO + (int64_t)((s_woff[k][wave] + loc[k]) & 0xFFFFu);
-      if (dest < a.cap) store4(a, dest, px[k], pvx[k], pvy[k], pvz[k]);
-      deposit_lds(sH, px[k], inv_dx, nx, 1ull, jlo, jhi);
-    }
-    if (any_rare) {
-#pragma unroll
-      for (int k = 0; k < kPPT; ++k) {
-        if (!is_rare<SP>(code[k])) continue;
-        const uint32_t off = s_woff[k][wave] + loc[k];
-        rare_particle<SP>(a, sH, s_cnt, base + k * kBlock + tid, code[k], px[k], pvx[k], pvy[k],
-                          pvz[k], prefO + (int64_t)(off & 0xFFFFu),
-                          bbase + prefB + (int64_t)(off >> 16), jlo, jhi);
-      }
-    }
-
-    // ---------------- flush the touched deposit range ----------------------
-    jlo = wave_min(jlo);
-    jhi = wave_max(jhi);
-    if (lane == 0) {
-      atomicMin(&s_lo, jlo);
-      atomicMax(&s_hi, jhi);
-    }
-    __syncthreads();
-    const int lo = s_lo, hi = s_hi;  // lo > hi when the tile deposited nothing
-    for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += kBlock) {
-      const unsigned long long v = sH[j];
-      if (v) {
-        atomicAdd(&a.dep_own[j], v);
-        sH[j] = 0ull;
-      }
-      if (MEASURE) {
-        const double e = sEW[j];
-        if (e != 0.0) {
-          atomicAdd(&a.acc_ew[j], e);
-          sEW[j] = 0.0;
-        }
-      }
-    }
-    __syncthreads();  // every thread has read s_lo/s_hi
-    if (tid == 0) {
-#if PIC_TICKETS
-      s_tile = (int)next_ticket;
-#endif
-      s_lo = INT_MAX;
-      s_hi = -1;
-    }
-    __syncthreads();
-#if PIC_TICKETS
-    t = uniform32(s_tile);
-#else
-    t += (int)gridDim.x;
-#endif
+  const int64_t n = a.ctl->n_rare[SP];
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const uint4 q = a.rq[i];
+    rare_slot<SP>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w);
   }
-
-  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
-  if (MEASURE) {
-    for (int b = tid; b < a.nbins; b += kBlock)
-      if (sEEPF[b]) atomicAdd(&a.eepf[b], (unsigned long long)sEEPF[b]);
-  }
+  __syncthreads();
+  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
 }
 
-size_t particle_lds_bytes(int nx, bool measure, int nbins) {
+// ---------------------------------------------------------------------------
+// host side
+
+static size_t decide_lds(int nx, bool measure, int nbins) {
   size_t b = (size_t)nx * 16;
   if (measure) b += (size_t)nx * 8 + (size_t)nbins * 4;
   return b;
 }
 
-int particle_blocks_per_cu(int species, bool measure, size_t lds) {
+static size_t emit_lds(int nx) { return (size_t)nx * 8; }
+
+template <typename K>
+static int blocks_per_cu(K kern, size_t lds) {
   int nb = 0;
-  hipError_t e;
-  if (species == 0)
-    e = measure ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particle<0, true>, kBlock, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particle<0, false>, kBlock, lds);
-  else
-    e = measure ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particle<1, true>, kBlock, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_particle<1, false>, kBlock, lds);
-  if (e != hipSuccess || nb < 1) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, lds) != hipSuccess || nb < 1)
+    nb = 1;
   return nb;
 }
 
-template <typename K>
-static hipError_t launch_one(K kern, int grid, size_t lds, const PartArgs& a, hipStream_t s) {
-#if PIC_COOP
-  void* args[] = {const_cast<PartArgs*>(&a)};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(kBlock),
-                                    args, (unsigned)lds, s);
-#else
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, a);
-  return hipGetLastError();
-#endif
+static int clamp_grid(int64_t g, int64_t max_tiles) {
+  if (g > max_tiles) g = max_tiles;
+  if (g < 1) g = 1;
+  return (int)g;
 }
 
-hipError_t launch_particles(int species, bool measure, const PartArgs& a, int grid, size_t lds,
-                            hipStream_t s) {
-  if (species == 0)
-    return measure ? launch_one(k_particle<0, true>, grid, lds, a, s)
-                   : launch_one(k_particle<0, false>, grid, lds, a, s);
-  return launch_one(k_particle<1, false>, grid, lds, a, s);
+PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, int64_t max_tiles) {
+  PartLaunch c{};
+  for (int m = 0; m < 2; ++m) {
+    c.lds_decide[m] = decide_lds(nx, m == 1, nbins);
+    int bpc;
+    if (species == 0)
+      bpc = m ? blocks_per_cu(k_decide<0, true>, c.lds_decide[m])
+              : blocks_per_cu(k_decide<0, false>, c.lds_decide[m]);
+    else
+      bpc = blocks_per_cu(k_decide<1, false>, c.lds_decide[m]);
+    c.grid_decide[m] = clamp_grid((int64_t)bpc * num_cu, max_tiles);
+  }
+  c.lds_emit = emit_lds(nx);
+  const int bpc = species == 0 ? blocks_per_cu(k_emit<0>, c.lds_emit)
+                               : blocks_per_cu(k_emit<1>, c.lds_emit);
+  c.grid_emit = clamp_grid((int64_t)bpc * num_cu, max_tiles);
+  c.grid_rare = num_cu * 2;
+  return c;
+}
+
+hipError_t launch_particle_kernel(int kernel, int species, bool measure, const PartArgs& a,
+                                  const PartLaunch& c, hipStream_t s) {
+  const int m = (species == 0 && measure) ? 1 : 0;
+  if (kernel == 0) {
+    if (species == 1)
+      hipLaunchKernelGGL((k_decide<1, false>), dim3(c.grid_decide[0]), dim3(kBlock),
+                         c.lds_decide[0], s, a);
+    else if (m)
+      hipLaunchKernelGGL((k_decide<0, true>), dim3(c.grid_decide[1]), dim3(kBlock),
+                         c.lds_decide[1], s, a);
+    else
+      hipLaunchKernelGGL((k_decide<0, false>), dim3(c.grid_decide[0]), dim3(kBlock),
+                         c.lds_decide[0], s, a);
+  } else if (kernel == 1) {
+    if (species == 0)
+      hipLaunchKernelGGL((k_emit<0>), dim3(c.grid_emit), dim3(kBlock), c.lds_emit, s, a);
+    else
+      hipLaunchKernelGGL((k_emit<1>), dim3(c.grid_emit), dim3(kBlock), c.lds_emit, s, a);
+  } else {
+    if (species == 0)
+      hipLaunchKernelGGL((k_rare<0>), dim3(c.grid_rare), dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_rare<1>), dim3(c.grid_rare), dim3(kBlock), 0, s, a);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace pic

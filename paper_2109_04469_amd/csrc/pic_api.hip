@@ -19,7 +19,7 @@ constexpr int kMaxCells = 4096;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-  size_t ctl, part[2][2][4], codes[2], tstat[2], dep_e[2], dep_i[2], rho, phi, E, cum[2], th_cp,
+  size_t ctl, part[2][2][4], codes[2], tcnt[2], rq[2], dep_e[2], dep_i[2], rho, phi, E, cum[2], th_cp,
       th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, sort_cnt, sort_seg, total;
   int64_t max_tiles[2];
   int sort_blocks;
@@ -68,7 +68,8 @@ Layout make_layout(const pic_params* p, const pic_xsec* xs) {
     for (int b = 0; b < 2; ++b)
       for (int q = 0; q < 4; ++q) L.part[s][b][q] = take((size_t)cap * sizeof(double));
     L.codes[s] = take((size_t)cap);
-    L.tstat[s] = take((size_t)L.max_tiles[s] * 2 * sizeof(uint64_t));
+    L.tcnt[s] = take((size_t)L.max_tiles[s] * sizeof(uint64_t));
+    L.rq[s] = take((size_t)cap * 16);
   }
   for (int b = 0; b < 2; ++b) L.dep_e[b] = take((size_t)nx * 8);
   for (int b = 0; b < 2; ++b) L.dep_i[b] = take((size_t)nx * 8);
@@ -106,14 +107,16 @@ int hip_status(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EHIP; }
 // Starts a timed launch: returns the event index or -1 when timing is off.
 int timer_begin(pic_handle* h) {
   if (!h->timing) return -1;
-  const size_t need = 2 * (h->ev_used.size() + 1);
+  const size_t need = 2 * (h->ev_next + 1);
   while (h->ev_pool.size() < need) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return -1;
+    // timing-only events: no system-scope fence (no cache writeback) on record
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -1;
     h->ev_pool.push_back(e);
   }
-  const int idx = (int)(2 * h->ev_used.size());
+  const int idx = (int)(2 * h->ev_next);
   if (hipEventRecord(h->ev_pool[idx], h->stream) != hipSuccess) return -1;
+  h->ev_next += 1;
   return idx;
 }
 
@@ -125,7 +128,10 @@ void timer_end(pic_handle* h, int timer, int idx) {
 
 // Folds the recorded event pairs into the per-timer sums (synchronises).
 int timer_collect(pic_handle* h) {
-  if (h->ev_used.empty()) return PIC_OK;
+  if (h->ev_used.empty()) {
+    h->ev_next = 0;
+    return PIC_OK;
+  }
   if (hipStreamSynchronize(h->stream) != hipSuccess) return PIC_EHIP;
   for (const auto& u : h->ev_used) {
     float ms = 0.f;
@@ -135,6 +141,7 @@ int timer_collect(pic_handle* h) {
     h->t_n[u.first] += 1;
   }
   h->ev_used.clear();
+  h->ev_next = 0;
   return PIC_OK;
 }
 
@@ -142,7 +149,6 @@ int latched(pic_handle* h) {
   uint32_t err = 0;
   HIP_TRY(hipMemcpyAsync(&err, &h->ctl->err, sizeof(err), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
-  if (err & kErrLookback) return PIC_EHIP;
   if (err & kErrUnstable) return PIC_EUNSTABLE;
   if (err & kErrCapacity) return PIC_ECAPACITY;
   return PIC_OK;
@@ -185,7 +191,8 @@ PartArgs particle_args(pic_handle* h, int sp, int parity) {
   }
   a.cum = h->cum[sp];
   a.ctl = h->ctl;
-  a.tstat = h->tstat[sp];
+  a.tcnt = h->tcnt[sp];
+  a.rq = h->rq[sp];
   a.codes = h->codes[sp];
   a.acc_ew = h->acc_ew;
   a.eepf = h->eepf;
@@ -218,7 +225,6 @@ PartArgs particle_args(pic_handle* h, int sp, int parity) {
   a.step = (uint32_t)h->step;
   a.seed = h->p.seed;
   a.run = h->p.run;
-  a.epoch = ++h->epoch;
   a.no_coll = (h->p.flags & PIC_FLAG_NO_COLL) ? 1 : 0;
   a.record = (h->p.flags & PIC_FLAG_RECORD) ? 1 : 0;
   return a;
@@ -366,7 +372,8 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
     for (int b = 0; b < 2; ++b)
       for (int q = 0; q < 4; ++q) h->part[s][b][q] = reinterpret_cast<double*>(w + L.part[s][b][q]);
     h->codes[s] = reinterpret_cast<uint8_t*>(w + L.codes[s]);
-    h->tstat[s] = reinterpret_cast<uint64_t*>(w + L.tstat[s]);
+    h->tcnt[s] = reinterpret_cast<uint64_t*>(w + L.tcnt[s]);
+    h->rq[s] = reinterpret_cast<uint4*>(w + L.rq[s]);
     h->max_tiles[s] = L.max_tiles[s];
     h->cum[s] = reinterpret_cast<double*>(w + L.cum[s]);
   }
@@ -391,7 +398,6 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
   h->cur[0] = h->cur[1] = 0;
   h->cur_hi = 0;
   h->measuring = 0;
-  h->epoch = 0;
 
   int st = PIC_OK;
   if (hipMemsetAsync(workspace, 0, L.total, h->stream) != hipSuccess ||
@@ -409,16 +415,8 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
     delete h;
     return st;
   }
-  for (int m = 0; m < 2; ++m) {
-    h->lds[m] = particle_lds_bytes(h->nx, m == 1, p->eepf_bins);
-    for (int s = 0; s < 2; ++s) {
-      const int bpc = particle_blocks_per_cu(s, m == 1 && s == 0, h->lds[m]);
-      int64_t g = (int64_t)bpc * h->num_cu;
-      if (g > h->max_tiles[s]) g = h->max_tiles[s];
-      if (g < 1) g = 1;
-      h->grid[s][m] = (int)g;
-    }
-  }
+  for (int s = 0; s < 2; ++s)
+    h->launch[s] = particle_launch_config(s, h->nx, p->eepf_bins, h->num_cu, h->max_tiles[s]);
   h->d.n_x = h->nx;
   h->d.n_tiles_max = (int32_t)(L.max_tiles[0] > L.max_tiles[1] ? L.max_tiles[0] : L.max_tiles[1]);
   h->d.dx = h->dx;
@@ -500,6 +498,22 @@ int pic_get_state(pic_handle* h, int species, double* x, double* vx, double* vy,
   return PIC_OK;
 }
 
+// One species' particle pass: decide, emit and rare kernels, each timed on
+// its own and the three together.
+int particle_pass(pic_handle* h, int sp, const PartArgs& a) {
+  static const int kTimer[2][3] = {{PIC_TIMER_E_DECIDE, PIC_TIMER_E_EMIT, PIC_TIMER_E_RARE},
+                                   {PIC_TIMER_I_DECIDE, PIC_TIMER_I_EMIT, PIC_TIMER_I_RARE}};
+  const bool measure = sp == 0 && h->measuring;
+  const int pass = timer_begin(h);
+  for (int k = 0; k < 3; ++k) {
+    const int ev = h->timing >= 2 ? timer_begin(h) : -1;
+    HIP_TRY(launch_particle_kernel(k, sp, measure, a, h->launch[sp], h->stream));
+    timer_end(h, kTimer[sp][k], ev);
+  }
+  timer_end(h, sp == 0 ? PIC_TIMER_ELECTRON : PIC_TIMER_ION, pass);
+  return PIC_OK;
+}
+
 int pic_step(pic_handle* h, int64_t n_steps) {
   if (!h || n_steps < 0) return PIC_EINVAL;
   if ((h->p.flags & PIC_FLAG_FIXED_E) && !h->field_fixed_set) return PIC_ESTATE;
@@ -536,17 +550,14 @@ int pic_step(pic_handle* h, int64_t n_steps) {
     HIP_TRY(launch_field(f, h->stream));
     timer_end(h, PIC_TIMER_FIELD, ev);
 
-    const int m = h->measuring ? 1 : 0;
     PartArgs ae = particle_args(h, 0, par);
-    ev = timer_begin(h);
-    HIP_TRY(launch_particles(0, m == 1, ae, h->grid[0][m], h->lds[m], h->stream));
-    timer_end(h, PIC_TIMER_ELECTRON, ev);
+    int st = particle_pass(h, 0, ae);
+    if (st) return st;
     h->cur[0] ^= 1;
     if (ion_step) {
       PartArgs ai = particle_args(h, 1, par);
-      ev = timer_begin(h);
-      HIP_TRY(launch_particles(1, false, ai, h->grid[1][0], h->lds[0], h->stream));
-      timer_end(h, PIC_TIMER_ION, ev);
+      st = particle_pass(h, 1, ai);
+      if (st) return st;
       h->cur[1] ^= 1;
       h->cur_hi ^= 1;
     }
@@ -665,9 +676,9 @@ int pic_get_decisions(pic_handle* h, int species, uint8_t* codes, int64_t cap, i
   return latched(h);
 }
 
-int pic_timing(pic_handle* h, int on) {
-  if (!h) return PIC_EINVAL;
-  h->timing = on ? 1 : 0;
+int pic_timing(pic_handle* h, int level) {
+  if (!h || level < 0 || level > 2) return PIC_EINVAL;
+  h->timing = level;
   return PIC_OK;
 }
 
@@ -707,6 +718,13 @@ int pic_selftest_sqrt(const double* in, double* out, int64_t n, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HIP_TRY(launch_selftest_sqrt(in, out, n, s));
   HIP_TRY(hipStreamSynchronize(s));
+  return PIC_OK;
+}
+
+int pic_selftest_copy(const double* in, double* out, int64_t n, void* stream) {
+  if (n < 0 || (n & 1) || (n > 0 && (!in || !out))) return PIC_EINVAL;
+  if (((uintptr_t)in | (uintptr_t)out) & 15) return PIC_EINVAL;
+  HIP_TRY(launch_selftest_copy(in, out, n, (hipStream_t)stream));
   return PIC_OK;
 }
 

@@ -5,7 +5,9 @@
 // contraction (-ffp-contract=off), correctly rounded division and sqrt, CIC
 // weights in 2^-32 fixed point with integer accumulation, and all random
 // draws from Philox4x32-10 keyed by (seed, run) with counter
-// (step, slot, 16*species + purpose, 0).
+// (step, slot, 16*species + purpose, 0), except the collision-candidacy
+// uniform of slot i: word i mod 4 of the block (step, i / 4, 16*species + 4,
+// 0).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +21,7 @@ constexpr int kBlock = 256;          // threads per particle workgroup (4 waves)
 #endif
 constexpr int kPPT = PIC_PPT;        // particles per thread per tile
 constexpr int kTile = kBlock * kPPT;  // particles per tile
+static_assert(kPPT % 4 == 0, "k_decide takes runs of four slots");
 constexpr int kWave = 64;
 
 constexpr double kTwoPi = 6.283185307179586;
@@ -29,7 +32,6 @@ constexpr int64_t kOne32 = 4294967296LL;
 // latched device error bits
 constexpr uint32_t kErrUnstable = 1u;
 constexpr uint32_t kErrCapacity = 2u;
-constexpr uint32_t kErrLookback = 8u;  // a tile's prefix wait hit its bound
 
 // decision code bits (per pushed slot)
 constexpr uint8_t kCodePushed = 0x80;
@@ -49,8 +51,8 @@ struct DevCtl {
   int64_t i_births;   // ions appended by this step's electron kernel
   int64_t ncodes[2];  // slots with a decision code from the last step
   int64_t msteps;     // measured steps
+  int64_t n_rare[2];  // slots queued for the rare pass of the last step
   unsigned long long counters[NCOUNTERS];
-  uint32_t ticket[2];
   uint32_t err;
   uint32_t pad;
 };
@@ -138,15 +140,6 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
 
 __device__ __forceinline__ void latch_error(DevCtl* ctl, uint32_t bit) {
   atomicOr(&ctl->err, bit);
-}
-
-// ---------------------------------------------------------------------------
-// agent-scope atomic helpers (the status words of the decoupled look-back)
-__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // wave-level inclusive scan (64 lanes)

@@ -64,7 +64,8 @@ struct PartArgs {
   unsigned long long* dep_other;  // deposit of the other species' births
   const double* cum;              // cumulative nu tables, nproc x ntab
   DevCtl* ctl;
-  uint64_t* tstat;  // look-back status words, 2 per tile
+  uint64_t* tcnt;   // per tile: outputs | births << 16 | queued slots << 32
+  uint4* rq;        // queued slots: (slot, code, output slot, birth slot)
   uint8_t* codes;
   double* acc_ew;                // CIC-weighted energy (electrons, measuring)
   unsigned long long* eepf;     // EEPF histogram (electrons, measuring)
@@ -97,7 +98,6 @@ struct PartArgs {
   uint32_t step;
   uint32_t seed;
   uint32_t run;
-  uint32_t epoch;
   int no_coll;
   int record;
 };
@@ -116,16 +116,25 @@ struct SortArgs {
 
 // host launchers
 hipError_t launch_field(const FieldArgs& a, hipStream_t s);
-hipError_t launch_particles(int species, bool measure, const PartArgs& a, int grid, size_t lds,
-                            hipStream_t s);
-size_t particle_lds_bytes(int nx, bool measure, int nbins);
-int particle_blocks_per_cu(int species, bool measure, size_t lds);
+// grid and LDS bytes of one species' two particle kernels
+struct PartLaunch {
+  int grid_decide[2];  // [measuring]
+  size_t lds_decide[2];
+  int grid_emit;
+  size_t lds_emit;
+  int grid_rare;
+};
+PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, int64_t max_tiles);
+// kernel 0: k_decide, 1: k_emit, 2: k_rare (launched in this order)
+hipError_t launch_particle_kernel(int kernel, int species, bool measure, const PartArgs& a,
+                                  const PartLaunch& c, hipStream_t s);
 hipError_t launch_sort(const SortArgs& a, hipStream_t s);
 hipError_t launch_deposit(const double* x, const int64_t* count, double inv_dx, int nx,
                           unsigned long long* dep, hipStream_t s);
 hipError_t launch_selftest_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                                   int64_t n, hipStream_t s);
 hipError_t launch_selftest_sqrt(const double* in, double* out, int64_t n, hipStream_t s);
+hipError_t launch_selftest_copy(const double* in, double* out, int64_t n, hipStream_t s);
 
 }  // namespace pic
 
@@ -149,7 +158,8 @@ struct pic_handle {
   pic::DevCtl* ctl;
   double* part[2][2][4];  // [species][buffer][x, vx, vy, vz]
   uint8_t* codes[2];
-  uint64_t* tstat[2];
+  uint64_t* tcnt[2];
+  uint4* rq[2];
   int64_t max_tiles[2];
   int64_t* dep_e[2];
   int64_t* dep_i[2];
@@ -173,13 +183,12 @@ struct pic_handle {
   int cur_hi;
   int measuring;
   int field_fixed_set;
-  uint32_t epoch;
-  int grid[2][2];     // [species][measure]
-  size_t lds[2];      // [measure]
+  pic::PartLaunch launch[2];  // [species]
   // opt-in kernel timing: event pairs recorded around launches
   int timing;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, int>> ev_used;  // (timer, index of start event)
+  size_t ev_next = 0;                        // event pairs handed out since the last fold
   double t_ms[PIC_NTIMERS];
   int64_t t_n[PIC_NTIMERS];
 };

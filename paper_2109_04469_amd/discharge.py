@@ -174,8 +174,10 @@ class Discharge:
         check(self.L.pic_get_decisions(self.h, species, _ptr(buf), cap, ctypes.byref(n)), "pic_get_decisions")
         return buf[: n.value].copy()
 
-    def timing(self, on=True):
-        check(self.L.pic_timing(self.h, 1 if on else 0), "pic_timing")
+    def timing(self, level=1):
+        """0: off; 1: events around the field kernel, each species' particle
+        pass and each sort; 2: also around every single particle kernel."""
+        check(self.L.pic_timing(self.h, int(level)), "pic_timing")
 
     def get_timing(self, reset=False):
         ms = np.zeros(capi.NTIMERS)
@@ -208,3 +210,13 @@ def selftest_sqrt(x: np.ndarray, device="cuda:0"):
     s = torch.cuda.current_stream(torch.device(device))
     check(L.pic_selftest_sqrt(_ptr(t), _ptr(out), t.numel(), ctypes.c_void_p(s.cuda_stream)), "selftest_sqrt")
     return out.cpu().numpy()
+
+
+def selftest_copy(src: "torch.Tensor", dst: "torch.Tensor"):
+    """Enqueues the library's plain streaming copy of src into dst (float64
+    device tensors of equal, even length) on the current stream."""
+    L = capi.load()
+    assert src.dtype == torch.float64 and dst.dtype == torch.float64 and src.numel() == dst.numel()
+    s = torch.cuda.current_stream(src.device)
+    check(L.pic_selftest_copy(_ptr(src), _ptr(dst), src.numel(), ctypes.c_void_p(s.cuda_stream)),
+          "selftest_copy")

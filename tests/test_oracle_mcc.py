@@ -214,3 +214,32 @@ def test_speed_beyond_table_uses_last_entry(ora):
     assert c[15] == (code > 0).sum() > 0      # every candidate was beyond the table
     assert (code == 1).sum() == 0             # and none was a null event
     assert c[8] == (code == 2).sum()
+
+
+def test_candidacy_draws_are_independent_within_a_block(ora):
+    # Four consecutive slots share one Philox block for their candidacy
+    # uniforms (one word each). With P_coll = 1/2 the 16 candidacy patterns
+    # of a group of four slots must be equally likely: a reused or shifted
+    # word would concentrate them (e.g. on 0000 and 1111).
+    vtop = 4e6
+    p = params(gap_m=1e3, n_cells=16, pressure_pa=50.0, flags=NO_FIELD | RECORD, sort_interval=0,
+               capacity=(40_000, 8))
+    ng = p["pressure_pa"] / (KB * p["gas_temp_k"])
+    sigma = np.log(2.0) / (ng * vtop * dt_of(p))
+    xs = table_for(vtop, 1e5, n=513, sig_e=(sigma, 0.0, 0.0))
+    sim = ora.Oracle(p, xs)
+    assert abs(sim.derived()["p_coll_e"] - 0.5) < 1e-9
+    n = 40_000
+    rng = np.random.default_rng(5)
+    sim.set_state(0, rng.uniform(400, 600, n), *iso_velocities(n, 0.5 * vtop, rng))
+    sim.set_state(1, np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0))
+    chi2 = []
+    for _ in range(3):
+        sim.step(1)
+        cand = (_code_coll(sim.decisions(0)) != 0).astype(int).reshape(-1, 4)
+        assert abs(cand.mean() - 0.5) < 5 * np.sqrt(0.25 / n)
+        pattern = cand @ np.array([1, 2, 4, 8])
+        obs = np.bincount(pattern, minlength=16)
+        expect = n / 4 / 16
+        chi2.append(((obs - expect) ** 2 / expect).sum())
+    assert max(chi2) < 45, chi2  # 15 dof: 99.9% quantile ~ 37.7
