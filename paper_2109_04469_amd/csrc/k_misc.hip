@@ -41,6 +41,35 @@ __global__ void k_selftest_sqrt(const double* in, double* out, int64_t n) {
   if (i < n) out[i] = sqrt(in[i]);
 }
 
+__global__ __launch_bounds__(256) void k_iota(uint32_t* id, const int64_t* count) {
+  const int64_t n = *count;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    id[i] = (uint32_t)i;
+}
+
+hipError_t launch_iota(uint32_t* id, const int64_t* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_iota, dim3(1024), dim3(256), 0, s, id, count);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_gather(const uint32_t* id, const double* vy,
+                                                const double* vz, double* out_y, double* out_z,
+                                                int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t k = id[i];
+    out_y[i] = vy[k];
+    out_z[i] = vz[k];
+  }
+}
+
+hipError_t launch_gather(const uint32_t* id, const double* vy, const double* vz, double* out_y,
+                         double* out_z, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_gather, dim3(1024), dim3(256), 0, s, id, vy, vz, out_y, out_z, n);
+  return hipGetLastError();
+}
+
 // Plain streaming copy, 16 bytes per lane per iteration: the reference
 // kernel for achievable HBM bandwidth and for scaling traffic counters.
 __global__ __launch_bounds__(256) void k_selftest_copy(const double2* __restrict__ in,

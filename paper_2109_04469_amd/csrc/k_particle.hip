@@ -219,8 +219,9 @@ __global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
           cell_of(x, inv_dx, nx, j, f, w1);
           double vy = 0.0, vz = 0.0;
           if (MEASURE) {
-            vy = a.vyin[slot];
-            vz = a.vzin[slot];
+            const uint32_t id = a.idin[slot];
+            vy = a.pvy[id];
+            vz = a.pvz[id];
             const double eps = a.ek * (vx * vx + vy * vy + vz * vz);
             atomicAdd(&sEW[j], ((double)(kOne32 - w1) * kInvTwo32) * eps);
             atomicAdd(&sEW[j + 1], ((double)w1 * kInvTwo32) * eps);
@@ -276,8 +277,9 @@ __global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
               // whether a second electron and an ion are born
               atomicAdd(&s_cnt[C_E_CAND], 1ull);
               if (!MEASURE) {
-                vy = a.vyin[slot];
-                vz = a.vzin[slot];
+                const uint32_t id = a.idin[slot];
+                vy = a.pvy[id];
+                vz = a.pvz[id];
               }
               const double g2 = sqrt(vx * vx + vy * vy + vz * vz);
               const double tv = g2 * a.inv_dv;
@@ -396,12 +398,11 @@ __global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
 // ---------------------------------------------------------------------------
 // k_emit
 
-__device__ __forceinline__ void store4(const PartArgs& a, int64_t i, double x, double vx, double vy,
-                                       double vz) {
+__device__ __forceinline__ void store3(const PartArgs& a, int64_t i, double x, double vx,
+                                       uint32_t id) {
   a.xout[i] = x;
   a.vxout[i] = vx;
-  a.vyout[i] = vy;
-  a.vzout[i] = vz;
+  a.idout[i] = id;
 }
 
 // k_decide's push and reflection, repeated on the slot's input state.
@@ -421,11 +422,13 @@ __device__ __forceinline__ void repush(const PartArgs& a, const double* E, uint3
 }
 
 __device__ __forceinline__ void reload(const PartArgs& a, const double* E, int64_t slot,
-                                       uint32_t c, double& x, double& vx, double& vy, double& vz) {
+                                       uint32_t c, double& x, double& vx, uint32_t& id,
+                                       double& vy, double& vz) {
   x = a.xin[slot];
   vx = a.vxin[slot];
-  vy = a.vyin[slot];
-  vz = a.vzin[slot];
+  id = a.idin[slot];
+  vy = a.pvy[id];
+  vz = a.pvz[id];
   repush(a, E, c, x, vx);
 }
 
@@ -434,6 +437,12 @@ __device__ __forceinline__ void reload(const PartArgs& a, const double* E, int64
 #define EMIT_GROUP 4
 #endif
 constexpr int kEmitGroup = EMIT_GROUP;
+#ifndef EMIT_EARLY
+#define EMIT_EARLY 0
+#endif
+// groups whose loads are issued before the tile scan
+constexpr int kEmitEarly = EMIT_EARLY;
+static_assert(kPPT * (kBlock / kWave) <= kWave, "one wave scans the segment totals");
 
 template <int SP>
 __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
@@ -459,6 +468,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   if (ntiles == 0) {
     if (blockIdx.x == 0 && tid == 0) {
       ctl->n_rare[SP] = 0;
+      ctl->pbase[0] = ctl->pool_n[0];
+      ctl->pbase[1] = ctl->pool_n[1];
       if (SP == 0) {
         ctl->e_out = 0;
         ctl->n_e[par ^ 1] = 0;
@@ -505,15 +516,25 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   for (int t = t0; t < t1; ++t) {
     const int64_t base = (int64_t)t * kTile;
     uint32_t code[kPPT], loc[kPPT];
+    double px[kPPT], pvx[kPPT];
+    uint32_t pid[kPPT];
 #pragma unroll
     for (int k = 0; k < kPPT; ++k) {
       const int64_t slot = base + k * kBlock + tid;
       uint32_t c = 0, cnt = 0;
+      px[k] = pvx[k] = 0.0;
+      pid[k] = 0u;
       if (slot < n_tot) {
         c = a.codes[slot];
         const Outcome oc = outcome<SP>(c);
         cnt = oc.own | (oc.birth << 16);
         c |= 0x100u;  // slot in range
+        if (k < kEmitEarly * kEmitGroup) {
+          // these loads do not wait for the scan
+          px[k] = a.xin[slot];
+          pvx[k] = a.vxin[slot];
+          pid[k] = a.idin[slot];
+        }
       }
       code[k] = c;
       const uint32_t inc = wave_incl_scan<unsigned int>(cnt);
@@ -521,29 +542,28 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
       if (lane == kWave - 1) s_wtot[k][wave] = inc;
     }
     __syncthreads();
-    if (tid == 0) {
-      uint32_t run = 0;
-      for (int k = 0; k < kPPT; ++k)
-        for (int w = 0; w < kBlock / kWave; ++w) {
-          s_woff[k][w] = run;
-          run += s_wtot[k][w];
-        }
-      s_agg = run;
+    if (wave == 0) {
+      // offsets of the (k, wave) segments, k-major: kPPT * 4 <= 64 values
+      const uint32_t* wt = &s_wtot[0][0];
+      uint32_t* wo = &s_woff[0][0];
+      const uint32_t v = lane < kPPT * (kBlock / kWave) ? wt[lane] : 0u;
+      const uint32_t inc = wave_incl_scan<unsigned int>(v);
+      if (lane < kPPT * (kBlock / kWave)) wo[lane] = inc - v;
+      if (lane == kPPT * (kBlock / kWave) - 1) s_agg = inc;
     }
     __syncthreads();
 
 #pragma unroll
     for (int g = 0; g < kPPT; g += kEmitGroup) {
-      double px[kEmitGroup], pvx[kEmitGroup], pvy[kEmitGroup], pvz[kEmitGroup];
+      if (g >= kEmitEarly * kEmitGroup) {
 #pragma unroll
-      for (int q = 0; q < kEmitGroup; ++q) {
-        const int64_t slot = base + (g + q) * kBlock + tid;
-        px[q] = pvx[q] = pvy[q] = pvz[q] = 0.0;
-        if (code[g + q] & 0x100u) {
-          px[q] = a.xin[slot];
-          pvx[q] = a.vxin[slot];
-          pvy[q] = a.vyin[slot];
-          pvz[q] = a.vzin[slot];
+        for (int q = 0; q < kEmitGroup; ++q) {
+          const int64_t slot = base + (g + q) * kBlock + tid;
+          if (code[g + q] & 0x100u) {
+            px[g + q] = a.xin[slot];
+            pvx[g + q] = a.vxin[slot];
+            pid[g + q] = a.idin[slot];
+          }
         }
       }
 #pragma unroll
@@ -564,14 +584,14 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
             const int64_t pos = prefR + qb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
             a.rq[pos] = make_uint4((uint32_t)(base + k * kBlock + tid), c & 0xFFu,
                                    (uint32_t)(prefO + (off & 0xFFFFu)),
-                                   (uint32_t)(bbase + prefB + (off >> 16)));
+                                   (uint32_t)(prefB + (off >> 16)));
           }
         }
         if (!in || rare || !oc.own) continue;
         const int64_t dest = prefO + (int64_t)(off & 0xFFFFu);
-        double x = px[q], vx = pvx[q];
+        double x = px[k], vx = pvx[k];
         repush(a, sE, c, x, vx);
-        if (dest < a.cap) store4(a, dest, x, vx, pvy[q], pvz[q]);
+        if (dest < a.cap) store3(a, dest, x, vx, pid[k]);
       }
     }
     __syncthreads();
@@ -591,6 +611,15 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
         ctl->n_e[par ^ 1] = bbase + prefB;
       }
       if (prefO > a.cap || bbase + prefB > a.bcap) latch_error(ctl, kErrCapacity);
+      // pool entries of this pass's births: an ionization takes one in each
+      // pool (the new electron and the new ion), an emission one electron
+      // entry; k_rare fills them from these bases
+      const int other = 1 - SP;
+      ctl->pbase[SP] = ctl->pool_n[SP];
+      ctl->pbase[other] = ctl->pool_n[other];
+      if (SP == 0) ctl->pool_n[SP] += prefB;
+      ctl->pool_n[other] += prefB;
+      if (ctl->pool_n[SP] > a.pcap || ctl->pool_n[other] > a.bpcap) latch_error(ctl, kErrCapacity);
     }
     __syncthreads();  // s_woff, s_agg and s_qn are reused by the next tile
     if (tid == 0) s_qn = 0;
@@ -601,15 +630,20 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
 // k_rare: the queued slots, one per thread
 
 // Collision kinematics, the ion process choice and secondary emission for
-// one slot, and its outputs at dest (own species) and bdest (births). E is
-// read from global memory here (the same values k_decide used).
+// one slot, and its outputs at dest (own species) and, for a birth of rank r
+// in this pass, at slot bbase + r of the other species with pool entries
+// pbase + r. E is read from global memory here (the same values k_decide
+// used).
 template <int SP>
 __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long* s_cnt,
-                          int64_t slot, uint32_t c, int64_t dest, int64_t bdest) {
+                                          int64_t slot, uint32_t c, int64_t dest, int64_t r,
+                                          int64_t bbase) {
   const uint32_t step = a.step;
   const double L = a.L;
+  const int64_t bdest = bbase + r;
   double x, vx, vy, vz;
-  reload(a, a.E, slot, c, x, vx, vy, vz);
+  uint32_t id;
+  reload(a, a.E, slot, c, x, vx, id, vy, vz);
   const Outcome oc = outcome<SP>(c);
   bool child = false;
   double cvx = 0, cvy = 0, cvz = 0, bxp = 0, bvx = 0, bvy = 0, bvz = 0;
@@ -711,14 +745,28 @@ __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long*
     bvz = a.sig_se * n3;
   }
   if (oc.own) {
-    if (dest < a.cap) store4(a, dest, x, vx, vy, vz);
-    if (child && dest + 1 < a.cap) store4(a, dest + 1, x, cvx, cvy, cvz);
+    // the particle keeps its pool entry
+    if (dest < a.cap) store3(a, dest, x, vx, id);
+    a.pvy[id] = vy;
+    a.pvz[id] = vz;
+    if (child) {
+      const int64_t cid = a.ctl->pbase[SP] + r;
+      if (dest + 1 < a.cap && cid < a.pcap) {
+        store3(a, dest + 1, x, cvx, (uint32_t)cid);
+        a.pvy[cid] = cvy;
+        a.pvz[cid] = cvz;
+      }
+    }
   }
-  if (oc.birth && bdest < a.bcap) {
-    a.bx[bdest] = bxp;
-    a.bvx[bdest] = bvx;
-    a.bvy[bdest] = bvy;
-    a.bvz[bdest] = bvz;
+  if (oc.birth) {
+    const int64_t bid = a.ctl->pbase[1 - SP] + r;
+    if (bdest < a.bcap && bid < a.bpcap) {
+      a.bx[bdest] = bxp;
+      a.bvx[bdest] = bvx;
+      a.bid[bdest] = (uint32_t)bid;
+      a.bpvy[bid] = bvy;
+      a.bpvz[bid] = bvz;
+    }
   }
 }
 
@@ -729,9 +777,11 @@ __global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
   if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
   __syncthreads();
   const int64_t n = a.ctl->n_rare[SP];
+  // births are appended after the other species' particles (as in k_emit)
+  const int64_t bbase = SP == 0 ? a.ctl->n_i[a.parity] : a.ctl->e_out;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < n; i += (int64_t)gridDim.x * kBlock) {
     const uint4 q = a.rq[i];
-    rare_slot<SP>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w);
+    rare_slot<SP>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
   }
   __syncthreads();
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(SortArgs a) {
   int64_t lo, hi;
   chunk_range(min(*a.count, a.cap), a.nblocks, blockIdx.x, lo, hi);
   for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads)
-    atomicAdd(&sh[cell_key(a.src[0][i], a.inv_dx, a.nx)], 1u);
+    atomicAdd(&sh[cell_key(a.sx[i], a.inv_dx, a.nx)], 1u);
   __syncthreads();
   for (int k = threadIdx.x; k < nkeys; k += kSortThreads)
     a.cnt[(size_t)k * a.nblocks + blockIdx.x] = sh[k];
@@ -123,12 +123,15 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs a) {
   for (int64_t b0 = lo; b0 < hi; b0 += kSortThreads) {
     const int64_t i = b0 + threadIdx.x;
     const bool valid = i < hi;
-    double v[4];
+    double x = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
     int key = 0;
     if (valid) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) v[q] = a.src[q][i];
-      key = cell_key(v[0], a.inv_dx, a.nx);
+      x = a.sx[i];
+      vx = a.svx[i];
+      const uint32_t id = a.sid[i];
+      vy = a.spvy[id];
+      vz = a.spvz[id];
+      key = cell_key(x, a.inv_dx, a.nx);
     }
     // lanes of this wave holding the same key
     uint64_t mask = __ballot(valid);
@@ -149,13 +152,38 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs a) {
       __syncthreads();
     }
     if (valid) {
+      // the sorted slot's pool entry is the slot itself
       const uint32_t dest = s_base[wave][leader] + (uint32_t)rank;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a.dst[q][dest] = v[q];
+      a.dx[dest] = x;
+      a.dvx[dest] = vx;
+      a.did[dest] = dest;
+      a.dpvy[dest] = vy;
+      a.dpvz[dest] = vz;
     }
     __syncthreads();
   }
 }
+
+// The pool in slot order without moving the slots: entry i of the new pool
+// is slot i's (v_y, v_z), and slot i's index becomes i.
+__global__ __launch_bounds__(kSortThreads) void k_repack(SortArgs a) {
+  const int64_t n = min(*a.count, a.cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.pool_n = n;
+  for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kSortThreads) {
+    const uint32_t id = a.sid[i];
+    a.dpvy[i] = a.spvy[id];
+    a.dpvz[i] = a.spvz[id];
+    a.did[i] = (uint32_t)i;
+  }
+}
+
+hipError_t launch_repack(const SortArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_repack, dim3(1024), dim3(kSortThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void k_sort_pool_n(SortArgs a) { *a.pool_n = min(*a.count, a.cap); }
 
 hipError_t launch_sort(const SortArgs& a, hipStream_t s) {
   const size_t lds = (size_t)(a.nx - 1) * sizeof(uint32_t);
@@ -164,6 +192,7 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanSegs), 0, s, a);
   hipLaunchKernelGGL(k_scan_down, dim3(kScanSegs), dim3(kSortThreads), 0, s, a);
   hipLaunchKernelGGL(k_sort_scatter, dim3(a.nblocks), dim3(kSortThreads), lds, s, a);
+  hipLaunchKernelGGL(k_sort_pool_n, dim3(1), dim3(1), 0, s, a);
   return hipGetLastError();
 }
 

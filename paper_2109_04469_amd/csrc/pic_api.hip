@@ -18,8 +18,14 @@ constexpr int kMaxCells = 4096;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Velocity-pool entries per buffer: the live particles plus the entries of
+// particles absorbed and born since the last repack (every sort, or every
+// kRepackSteps steps without sorting).
+constexpr int kRepackSteps = 32;
+int64_t pool_capacity(int64_t cap) { return cap + (cap / 4 > 4096 ? cap / 4 : 4096); }
+
 struct Layout {
-  size_t ctl, part[2][2][4], codes[2], tcnt[2], rq[2], dep_e[2], dep_i[2], rho, phi, E, cum[2], th_cp,
+  size_t ctl, part[2][2][2], pid[2][2], pool[2][2][2], codes[2], tcnt[2], rq[2], dep_e[2], dep_i[2], rho, phi, E, cum[2], th_cp,
       th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, sort_cnt, sort_seg, total;
   int64_t max_tiles[2];
   int sort_blocks;
@@ -65,8 +71,11 @@ Layout make_layout(const pic_params* p, const pic_xsec* xs) {
   for (int s = 0; s < 2; ++s) {
     const int64_t cap = p->capacity[s];
     L.max_tiles[s] = (cap + kTile - 1) / kTile + 1;
-    for (int b = 0; b < 2; ++b)
-      for (int q = 0; q < 4; ++q) L.part[s][b][q] = take((size_t)cap * sizeof(double));
+    for (int b = 0; b < 2; ++b) {
+      for (int q = 0; q < 2; ++q) L.part[s][b][q] = take((size_t)cap * sizeof(double));
+      L.pid[s][b] = take((size_t)cap * sizeof(uint32_t));
+      for (int q = 0; q < 2; ++q) L.pool[s][b][q] = take((size_t)pool_capacity(cap) * 8);
+    }
     L.codes[s] = take((size_t)cap);
     L.tcnt[s] = take((size_t)L.max_tiles[s] * sizeof(uint64_t));
     L.rq[s] = take((size_t)cap * 16);
@@ -167,20 +176,23 @@ PartArgs particle_args(pic_handle* h, int sp, int parity) {
   const int in = h->cur[sp], out = 1 - h->cur[sp];
   a.xin = h->part[sp][in][0];
   a.vxin = h->part[sp][in][1];
-  a.vyin = h->part[sp][in][2];
-  a.vzin = h->part[sp][in][3];
+  a.idin = h->pid[sp][in];
   a.xout = h->part[sp][out][0];
   a.vxout = h->part[sp][out][1];
-  a.vyout = h->part[sp][out][2];
-  a.vzout = h->part[sp][out][3];
+  a.idout = h->pid[sp][out];
+  a.pvy = h->pool[sp][h->pcur[sp]][0];
+  a.pvz = h->pool[sp][h->pcur[sp]][1];
+  a.pcap = h->pcap[sp];
   const int other = 1 - sp;
   // electrons append ions to the current ion buffer; ions append secondary
   // electrons to the electron buffer the electron kernel has just written
   const int ob = h->cur[other];
   a.bx = h->part[other][ob][0];
   a.bvx = h->part[other][ob][1];
-  a.bvy = h->part[other][ob][2];
-  a.bvz = h->part[other][ob][3];
+  a.bid = h->pid[other][ob];
+  a.bpvy = h->pool[other][h->pcur[other]][0];
+  a.bpvz = h->pool[other][h->pcur[other]][1];
+  a.bpcap = h->pcap[other];
   a.E = h->E;
   if (sp == 0) {
     a.dep_own = reinterpret_cast<unsigned long long*>(h->dep_e[parity ^ 1]);
@@ -230,13 +242,21 @@ PartArgs particle_args(pic_handle* h, int sp, int parity) {
   return a;
 }
 
-int sort_species(pic_handle* h, int sp) {
+SortArgs sort_args(pic_handle* h, int sp, bool reorder) {
   SortArgs a{};
-  const int in = h->cur[sp], out = 1 - h->cur[sp];
-  for (int q = 0; q < 4; ++q) {
-    a.src[q] = h->part[sp][in][q];
-    a.dst[q] = h->part[sp][out][q];
-  }
+  const int in = h->cur[sp], out = reorder ? 1 - h->cur[sp] : h->cur[sp];
+  const int pin = h->pcur[sp], pout = 1 - h->pcur[sp];
+  a.sx = h->part[sp][in][0];
+  a.svx = h->part[sp][in][1];
+  a.sid = h->pid[sp][in];
+  a.spvy = h->pool[sp][pin][0];
+  a.spvz = h->pool[sp][pin][1];
+  a.dx = h->part[sp][out][0];
+  a.dvx = h->part[sp][out][1];
+  a.did = h->pid[sp][out];
+  a.dpvy = h->pool[sp][pout][0];
+  a.dpvz = h->pool[sp][pout][1];
+  a.pool_n = &h->ctl->pool_n[sp];
   a.count = sp == 0 ? &h->ctl->n_e[h->step & 1] : &h->ctl->n_i[h->step & 1];
   a.cap = h->p.capacity[sp];
   a.cnt = h->sort_cnt;
@@ -244,10 +264,26 @@ int sort_species(pic_handle* h, int sp) {
   a.inv_dx = h->inv_dx;
   a.nx = h->nx;
   a.nblocks = h->sort_blocks;
+  return a;
+}
+
+// Stable sort of one species by cell; the pool is rebuilt in the new slot
+// order.
+int sort_species(pic_handle* h, int sp) {
+  const SortArgs a = sort_args(h, sp, true);
   const int ev = timer_begin(h);
   HIP_TRY(launch_sort(a, h->stream));
   timer_end(h, PIC_TIMER_SORT, ev);
-  h->cur[sp] = out;
+  h->cur[sp] ^= 1;
+  h->pcur[sp] ^= 1;
+  return PIC_OK;
+}
+
+// Pool rebuilt in slot order, slots unchanged: drops the entries of
+// absorbed particles.
+int repack_species(pic_handle* h, int sp) {
+  HIP_TRY(launch_repack(sort_args(h, sp, false), h->stream));
+  h->pcur[sp] ^= 1;
   return PIC_OK;
 }
 
@@ -369,8 +405,14 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
   char* w = static_cast<char*>(workspace);
   h->ctl = reinterpret_cast<DevCtl*>(w + L.ctl);
   for (int s = 0; s < 2; ++s) {
-    for (int b = 0; b < 2; ++b)
-      for (int q = 0; q < 4; ++q) h->part[s][b][q] = reinterpret_cast<double*>(w + L.part[s][b][q]);
+    for (int b = 0; b < 2; ++b) {
+      for (int q = 0; q < 2; ++q) {
+        h->part[s][b][q] = reinterpret_cast<double*>(w + L.part[s][b][q]);
+        h->pool[s][b][q] = reinterpret_cast<double*>(w + L.pool[s][b][q]);
+      }
+      h->pid[s][b] = reinterpret_cast<uint32_t*>(w + L.pid[s][b]);
+    }
+    h->pcap[s] = pool_capacity(p->capacity[s]);
     h->codes[s] = reinterpret_cast<uint8_t*>(w + L.codes[s]);
     h->tcnt[s] = reinterpret_cast<uint64_t*>(w + L.tcnt[s]);
     h->rq[s] = reinterpret_cast<uint4*>(w + L.rq[s]);
@@ -396,6 +438,7 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
   h->sort_blocks = L.sort_blocks;
   h->step = 0;
   h->cur[0] = h->cur[1] = 0;
+  h->pcur[0] = h->pcur[1] = 0;
   h->cur_hi = 0;
   h->measuring = 0;
 
@@ -457,13 +500,18 @@ int pic_set_state(pic_handle* h, int species, const double* x, const double* vx,
   }
   h->step = step;
   double* const* dst = h->part[species][h->cur[species]];
-  const double* src[4] = {x, vx, vy, vz};
-  for (int q = 0; q < 4; ++q)
-    if (n > 0)
-      HIP_TRY(hipMemcpyAsync(dst[q], src[q], (size_t)n * 8, hipMemcpyDefault, h->stream));
+  double* const* pool = h->pool[species][h->pcur[species]];
+  if (n > 0) {
+    HIP_TRY(hipMemcpyAsync(dst[0], x, (size_t)n * 8, hipMemcpyDefault, h->stream));
+    HIP_TRY(hipMemcpyAsync(dst[1], vx, (size_t)n * 8, hipMemcpyDefault, h->stream));
+    HIP_TRY(hipMemcpyAsync(pool[0], vy, (size_t)n * 8, hipMemcpyDefault, h->stream));
+    HIP_TRY(hipMemcpyAsync(pool[1], vz, (size_t)n * 8, hipMemcpyDefault, h->stream));
+  }
   int64_t nn = n;
   int64_t* cnt = species == 0 ? &h->ctl->n_e[par] : &h->ctl->n_i[par];
   HIP_TRY(hipMemcpyAsync(cnt, &nn, 8, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(&h->ctl->pool_n[species], &nn, 8, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(launch_iota(h->pid[species][h->cur[species]], cnt, h->stream));
   int64_t* dep = species == 0 ? h->dep_e[par] : h->dep_i[h->cur_hi];
   HIP_TRY(hipMemsetAsync(dep, 0, (size_t)h->nx * 8, h->stream));
   HIP_TRY(launch_deposit(dst[0], cnt, h->inv_dx, h->nx, reinterpret_cast<unsigned long long*>(dep),
@@ -487,12 +535,19 @@ int pic_get_state(pic_handle* h, int species, double* x, double* vx, double* vy,
   if (step) *step = h->step;
   if (err) return err;
   if (cnt > cap) return PIC_ECAPACITY;
-  double* out[4] = {x, vx, vy, vz};
-  for (int q = 0; q < 4; ++q) {
-    if (cnt > 0 && !out[q]) return PIC_EINVAL;
-    if (cnt > 0)
-      HIP_TRY(hipMemcpyAsync(out[q], h->part[species][h->cur[species]][q], (size_t)cnt * 8,
-                             hipMemcpyDefault, h->stream));
+  if (cnt > 0 && (!x || !vx || !vy || !vz)) return PIC_EINVAL;
+  if (cnt > 0) {
+    // v_y, v_z in slot order, gathered through the pool indices into the
+    // idle pool buffer
+    double* const* part = h->part[species][h->cur[species]];
+    double* const* pool = h->pool[species][h->pcur[species]];
+    double* const* tmp = h->pool[species][1 - h->pcur[species]];
+    HIP_TRY(launch_gather(h->pid[species][h->cur[species]], pool[0], pool[1], tmp[0], tmp[1], cnt,
+                          h->stream));
+    HIP_TRY(hipMemcpyAsync(x, part[0], (size_t)cnt * 8, hipMemcpyDefault, h->stream));
+    HIP_TRY(hipMemcpyAsync(vx, part[1], (size_t)cnt * 8, hipMemcpyDefault, h->stream));
+    HIP_TRY(hipMemcpyAsync(vy, tmp[0], (size_t)cnt * 8, hipMemcpyDefault, h->stream));
+    HIP_TRY(hipMemcpyAsync(vz, tmp[1], (size_t)cnt * 8, hipMemcpyDefault, h->stream));
   }
   HIP_TRY(hipStreamSynchronize(h->stream));
   return PIC_OK;
@@ -571,6 +626,11 @@ int pic_step(pic_handle* h, int64_t n_steps) {
       int s = sort_species(h, 0);
       if (s) return s;
       s = sort_species(h, 1);
+      if (s) return s;
+    } else if (h->step % kRepackSteps == 0) {
+      int s = repack_species(h, 0);
+      if (s) return s;
+      s = repack_species(h, 1);
       if (s) return s;
     }
   }

@@ -52,6 +52,8 @@ struct DevCtl {
   int64_t ncodes[2];  // slots with a decision code from the last step
   int64_t msteps;     // measured steps
   int64_t n_rare[2];  // slots queued for the rare pass of the last step
+  int64_t pool_n[2];  // velocity-pool entries in use (live + orphaned + new)
+  int64_t pbase[2];   // first pool entry of the last pass's births, per pool
   unsigned long long counters[NCOUNTERS];
   uint32_t err;
   uint32_t pad;
@@ -113,10 +115,10 @@ __device__ __forceinline__ void cell_of(double x, double inv_dx, int nx, int& j,
   if (jj < 0) jj = 0;
   j = jj;
   f = t - (double)jj;
-  int64_t w = (int64_t)floor(f * kTwo32 + 0.5);
-  if (w < 0) w = 0;
-  if (w > kOne32) w = kOne32;
-  w1 = w;
+  // round to nearest 2^-32 and clamp to [0, 2^32] in FP64, then convert
+  // through uint32 (one instruction) with 2^32 itself handled apart
+  const double wf = fmin(fmax(floor(f * kTwo32 + 0.5), 0.0), kTwo32);
+  w1 = wf >= kTwo32 ? kOne32 : (int64_t)(uint32_t)wf;
 }
 
 __device__ __forceinline__ int cell_key(double x, double inv_dx, int nx) {

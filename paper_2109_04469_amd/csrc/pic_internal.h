@@ -45,32 +45,39 @@ struct FieldArgs {
   int parity;
 };
 
+// Particle state of a species: x, v_x and a 4-byte pool index per slot in
+// ping-pong buffers, and v_y, v_z in a velocity pool at that index. A pass
+// moves (x, v_x, id); v_y and v_z stay in place unless a collision changes
+// them, and newborns take fresh pool entries.
 struct PartArgs {
   const double* xin;
   const double* vxin;
-  const double* vyin;
-  const double* vzin;
+  const uint32_t* idin;
   double* xout;
   double* vxout;
-  double* vyout;
-  double* vzout;
+  uint32_t* idout;
+  double* pvy;  // this species' velocity pool
+  double* pvz;
   // births of the other species are appended here
   double* bx;
   double* bvx;
-  double* bvy;
-  double* bvz;
+  uint32_t* bid;
+  double* bpvy;  // the other species' velocity pool
+  double* bpvz;
   const double* E;
   unsigned long long* dep_own;    // deposit of this kernel's outputs
   unsigned long long* dep_other;  // deposit of the other species' births
   const double* cum;              // cumulative nu tables, nproc x ntab
   DevCtl* ctl;
   uint64_t* tcnt;   // per tile: outputs | births << 16 | queued slots << 32
-  uint4* rq;        // queued slots: (slot, code, output slot, birth slot)
+  uint4* rq;        // queued slots: (slot, code, output slot, birth rank)
   uint8_t* codes;
   double* acc_ew;                // CIC-weighted energy (electrons, measuring)
   unsigned long long* eepf;     // EEPF histogram (electrons, measuring)
   int64_t cap;                  // capacity of the output arrays
   int64_t bcap;                 // capacity of the birth target arrays
+  int64_t pcap;                 // capacity of this species' pool
+  int64_t bpcap;                // capacity of the other species' pool
   int64_t max_tiles;
   double inv_dx;
   double L;
@@ -103,8 +110,17 @@ struct PartArgs {
 };
 
 struct SortArgs {
-  const double* src[4];
-  double* dst[4];
+  const double* sx;  // input: x, v_x, pool index, pool
+  const double* svx;
+  const uint32_t* sid;
+  const double* spvy;
+  const double* spvz;
+  double* dx;        // output in cell order, pool repacked in slot order
+  double* dvx;
+  uint32_t* did;
+  double* dpvy;
+  double* dpvz;
+  int64_t* pool_n;       // set to the count
   const int64_t* count;  // device count of the species
   int64_t cap;           // capacity of src/dst
   uint32_t* cnt;         // [nkeys][nblocks]
@@ -129,6 +145,13 @@ PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, in
 hipError_t launch_particle_kernel(int kernel, int species, bool measure, const PartArgs& a,
                                   const PartLaunch& c, hipStream_t s);
 hipError_t launch_sort(const SortArgs& a, hipStream_t s);
+// pool repacked in slot order (no reordering of the slots)
+hipError_t launch_repack(const SortArgs& a, hipStream_t s);
+// id[i] = i for i < *count
+hipError_t launch_iota(uint32_t* id, const int64_t* count, hipStream_t s);
+// out_y[i] = vy[id[i]], out_z[i] = vz[id[i]] for i < n
+hipError_t launch_gather(const uint32_t* id, const double* vy, const double* vz, double* out_y,
+                         double* out_z, int64_t n, hipStream_t s);
 hipError_t launch_deposit(const double* x, const int64_t* count, double inv_dx, int nx,
                           unsigned long long* dep, hipStream_t s);
 hipError_t launch_selftest_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
@@ -156,7 +179,10 @@ struct pic_handle {
   std::vector<double> vtab;
   // device memory (carved from the caller's workspace)
   pic::DevCtl* ctl;
-  double* part[2][2][4];  // [species][buffer][x, vx, vy, vz]
+  double* part[2][2][2];  // [species][buffer][x, vx]
+  uint32_t* pid[2][2];    // [species][buffer] pool index per slot
+  double* pool[2][2][2];  // [species][buffer][vy, vz]
+  int64_t pcap[2];        // pool entries per buffer
   uint8_t* codes[2];
   uint64_t* tcnt[2];
   uint4* rq[2];
@@ -180,6 +206,7 @@ struct pic_handle {
   // host-side schedule state
   int64_t step;
   int cur[2];
+  int pcur[2];  // active pool buffer per species
   int cur_hi;
   int measuring;
   int field_fixed_set;
