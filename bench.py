@@ -13,8 +13,10 @@ resident in HBM.
 
 value = particle-steps per second over the timed region (electrons every
 step, ions on their sub-cycled steps), from the library's own push counters.
-roofline: the electron particle pass (its decide, emit and rare kernels,
-launched back to back on the library's stream), algorithmic traffic 64 B per
+roofline: the electron particle pass (its decide and emit kernels and the
+kernel that takes its queued slots, launched back to back on the library's
+stream; on most steps that last kernel also solves the next step's field
+on one CU, which this figure charges to the pass), algorithmic traffic 64 B per
 particle-step (x, vx, vy, vz read and written in FP64) divided by the pass's
 mean duration from HIP events recorded on that stream, over a second window
 of the same length right after the timed one (event records slow a step by a
@@ -187,7 +189,9 @@ def main():
             achieved = bytes_per_launch / avg_s / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                    "kernel": "electron particle pass: k_decide<0> + k_emit<0> + k_rare<0>",
+                    "kernel": ("electron particle pass: k_decide<0> + k_emit<0> + k_tail<0> "
+                               "(its queued slots, overlapped with the next step's field); "
+                               "k_rare<0> instead of k_tail on ion steps"),
                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
                     "particles_per_launch": pe_w / en, "window_steps": steps}
 

@@ -1,278 +1,10 @@
-// Field kernel: charge density from the integer CIC deposits, the Poisson
-// solve with Dirichlet walls phi(0) = V(t), phi(L) = 0, and E by numerical
-// differentiation (arXiv:2109.04469, Sec. 2 steps 1-2). One workgroup: the
-// grid (<= 4097 nodes) lives in LDS.
-//
-// Default solver (FIELD_EXACT). With s_j = -dx^2 rho_j / eps0 = -K C_j, where
-// C_j is the net deposit in 2^-32 units (an exact int64), the finite
-// difference system phi_{j-1} - 2 phi_j + phi_{j+1} = s_j has the closed
-// solution
-//     D_j = phi_{j+1} - phi_j = D_0 - K Q_j,      Q_j = sum_{k=1..j} C_k
-//     phi_j = V + j D_0 - K R_j,                  R_j = sum_{i<j} Q_i
-//     D_0 = (K R_{N-1} - V) / (N - 1)             (from phi_{N-1} = 0)
-// so the solve is two integer prefix sums (exact, order-free, parallel)
-// followed by a few roundings per node, instead of a serial recurrence.
-// FIELD_THOMAS runs the textbook Thomas recurrence serially instead, with the
-// same operation order as the reference implementation (bitwise equal).
-#include "pic_internal.h"
+// Field kernel: the field step of arXiv:2109.04469, Sec. 2 steps 1-2, in one
+// workgroup (field_block.h).
+#include "field_block.h"
 
 namespace pic {
 
-constexpr int kFieldThreads = 1024;
-constexpr int kFieldWaves = kFieldThreads / kWave;
-constexpr int kMaxNx = 4097;
-constexpr int kFieldPer = (kMaxNx + kFieldThreads - 1) / kFieldThreads;  // 5
-
-struct i128p {
-  uint64_t lo;
-  int64_t hi;
-};
-
-__device__ __forceinline__ i128p add128(i128p a, i128p b) {
-  i128p r;
-  r.lo = a.lo + b.lo;
-  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1 : 0);
-  return r;
-}
-
-__device__ __forceinline__ i128p from64(int64_t v) {
-  i128p r;
-  r.lo = (uint64_t)v;
-  r.hi = v < 0 ? -1 : 0;
-  return r;
-}
-
-// nearest-ish double of a 128-bit integer: sign-magnitude, two roundings
-__device__ __forceinline__ double to_double(i128p v) {
-  bool neg = v.hi < 0;
-  if (neg) {  // two's complement negate
-    v.lo = ~v.lo + 1;
-    v.hi = ~v.hi + (v.lo == 0 ? 1 : 0);
-  }
-  const double r = (double)(uint64_t)v.hi * 18446744073709551616.0 + (double)v.lo;
-  return neg ? -r : r;
-}
-
-__device__ __forceinline__ i128p wave_incl_scan128(i128p v) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    i128p u;
-    u.lo = __shfl_up(v.lo, o, kWave);
-    u.hi = __shfl_up(v.hi, o, kWave);
-    if (lane >= o) v = add128(v, u);
-  }
-  return v;
-}
-
-// Block-wide exclusive scan of one int64 per thread; returns the total.
-__device__ int64_t block_excl_scan64(int64_t v, int64_t& excl, int64_t* s_wave) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const int64_t inc = wave_incl_scan<long long>((long long)v);
-  if (lane == kWave - 1) s_wave[wave] = inc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int w = 0; w < kFieldWaves; ++w) {
-      int64_t t = s_wave[w];
-      s_wave[w] = run;
-      run += t;
-    }
-    s_wave[kFieldWaves] = run;
-  }
-  __syncthreads();
-  excl = s_wave[wave] + inc - v;
-  const int64_t total = s_wave[kFieldWaves];
-  __syncthreads();
-  return total;
-}
-
-__device__ i128p block_excl_scan128(i128p v, i128p& excl, i128p* s_wave) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  const i128p inc = wave_incl_scan128(v);
-  if (lane == kWave - 1) s_wave[wave] = inc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    i128p run = from64(0);
-    for (int w = 0; w < kFieldWaves; ++w) {
-      i128p t = s_wave[w];
-      s_wave[w] = run;
-      run = add128(run, t);
-    }
-    s_wave[kFieldWaves] = run;
-  }
-  __syncthreads();
-  // excl = s_wave[wave] + inc - v
-  i128p neg_v;
-  neg_v.lo = ~v.lo + 1;
-  neg_v.hi = ~v.hi + (neg_v.lo == 0 ? 1 : 0);
-  excl = add128(add128(s_wave[wave], inc), neg_v);
-  const i128p total = s_wave[kFieldWaves];
-  __syncthreads();
-  return total;
-}
-
-__global__ __launch_bounds__(kFieldThreads) void k_field(FieldArgs a) {
-  __shared__ int64_t sC[kMaxNx];   // net deposit, then Q
-  __shared__ double sRho[kMaxNx];
-  __shared__ double sPhi[kMaxNx];
-  __shared__ int64_t s_wave64[kFieldWaves + 1];
-  __shared__ i128p s_wave128[kFieldWaves + 1];
-  __shared__ double sD0;
-
-  const int tid = threadIdx.x;
-  const int nx = a.nx;
-  if (tid == 0) {
-    a.ctl->ncodes[1] = 0;
-    a.ctl->counters[C_STEPS] += 1ull;
-    if (a.measuring) a.ctl->msteps += 1;
-  }
-  for (int j = tid; j < nx; j += kFieldThreads) {
-    if (a.zero_a) a.zero_a[j] = 0;
-    if (a.zero_b) a.zero_b[j] = 0;
-    const int64_t de = a.dep_e[j];
-    const int64_t di = a.dep_i[j];
-    const int64_t c = di - de;
-    sC[j] = c;
-    double r = (double)c * a.qfac32;
-    const bool wall = (j == 0) || (j == nx - 1);
-    if (wall) r = 2.0 * r;  // half-cell volume at the electrodes
-    sRho[j] = r;
-    a.rho[j] = r;
-    if (a.measuring) {
-      double ne = (double)de * a.nfac32;
-      double ni = (double)di * a.nfac32;
-      if (wall) {
-        ne = 2.0 * ne;
-        ni = 2.0 * ni;
-      }
-      a.acc_ne[j] += ne;
-      a.acc_ni[j] += ni;
-      a.acc_w[j] += (double)de * kInvTwo32;
-    }
-  }
-  __syncthreads();
-
-  if (a.mode == FIELD_ZERO || a.mode == FIELD_FIXED) {
-    for (int j = tid; j < nx; j += kFieldThreads) {
-      a.phi[j] = 0.0;
-      if (a.mode == FIELD_ZERO) a.E[j] = 0.0;
-    }
-    return;
-  }
-
-  const double dx = a.dx;
-  const double V = a.V;
-  if (a.mode == FIELD_THOMAS) {
-    // d_i = -(dx dx) rho_{i+1} / eps0 for the unknowns phi_1..phi_{N-2}
-    const int n = nx - 2;
-    for (int i = tid; i < n; i += kFieldThreads) sPhi[i + 1] = -(dx * dx) * sRho[i + 1] / kEps0;
-    __syncthreads();
-    if (tid == 0) {
-      // forward elimination: dp_i = (d_i - dp_{i-1}) / m_i, stored in place
-      double prev = (sPhi[1] - V) / -2.0;
-      if (n == 1) prev = ((sPhi[1] - V) - 0.0) / -2.0;
-      sPhi[1] = prev;
-      for (int i = 1; i < n; ++i) {
-        double d = sPhi[i + 1];
-        if (i == n - 1) d = d - 0.0;
-        prev = (d - prev) / a.th_m[i];
-        sPhi[i + 1] = prev;
-      }
-      // back substitution: y_i = dp_i - cp_i y_{i+1}
-      double y = prev;
-      for (int i = n - 2; i >= 0; --i) {
-        y = sPhi[i + 1] - a.th_cp[i] * y;
-        sPhi[i + 1] = y;
-      }
-      sPhi[0] = V;
-      sPhi[nx - 1] = 0.0;
-    }
-    __syncthreads();
-    for (int j = tid; j < nx; j += kFieldThreads) {
-      double e;
-      if (j == 0)
-        e = (sPhi[0] - sPhi[1]) / dx - sRho[0] * dx / (2.0 * kEps0);
-      else if (j == nx - 1)
-        e = (sPhi[nx - 2] - sPhi[nx - 1]) / dx + sRho[nx - 1] * dx / (2.0 * kEps0);
-      else
-        e = (sPhi[j - 1] - sPhi[j + 1]) / (2.0 * dx);
-      a.phi[j] = sPhi[j];
-      a.E[j] = e;
-      if (!isfinite(e)) latch_error(a.ctl, kErrUnstable);
-    }
-    return;
-  }
-
-  // ---- exact integer prefix form ----------------------------------------
-  // c_0 = 0, c_k = C_k (k = 1..N-2); Q = inclusive scan of c over N-1 entries
-  const int m = nx - 1;
-  const int per = (m + kFieldThreads - 1) / kFieldThreads;
-  const int b0 = tid * per;
-  int64_t loc[kFieldPer];
-  int64_t s = 0;
-#pragma unroll
-  for (int q = 0; q < kFieldPer; ++q) {
-    const int k = b0 + q;
-    int64_t c = 0;
-    if (q < per && k < m && k >= 1) c = sC[k];
-    s += c;
-    loc[q] = s;  // local inclusive
-  }
-  int64_t excl;
-  block_excl_scan64(s, excl, s_wave64);
-  // Q_k = excl + loc[q]; R contributions: sum of own Q's
-  i128p rsum = from64(0);
-#pragma unroll
-  for (int q = 0; q < kFieldPer; ++q) {
-    const int k = b0 + q;
-    if (q < per && k < m) {
-      const int64_t Qk = excl + loc[q];
-      loc[q] = Qk;
-      rsum = add128(rsum, from64(Qk));
-    }
-  }
-  i128p rexcl;
-  const i128p rtot = block_excl_scan128(rsum, rexcl, s_wave128);
-  // write Q into sC (after everyone has read C)
-#pragma unroll
-  for (int q = 0; q < kFieldPer; ++q) {
-    const int k = b0 + q;
-    if (q < per && k < m) sC[k] = loc[q];
-  }
-  if (tid == 0) sD0 = (a.kpois * to_double(rtot) - V) / (double)(nx - 1);
-  __syncthreads();
-  const double D0 = sD0;
-  const double K = a.kpois;
-  // potential: phi_j = V + j D0 - K R_j, R_j = sum_{i<j} Q_i
-  {
-    i128p r = rexcl;
-#pragma unroll
-    for (int q = 0; q < kFieldPer; ++q) {
-      const int k = b0 + q;
-      if (q < per && k < m) {
-        a.phi[k] = V + (double)k * D0 - K * to_double(r);
-        r = add128(r, from64(loc[q]));
-      }
-    }
-    if (tid == 0) a.phi[nx - 1] = 0.0;
-  }
-  for (int j = tid; j < nx; j += kFieldThreads) {
-    double e;
-    if (j == 0) {
-      e = -D0 / dx - sRho[0] * dx / (2.0 * kEps0);
-    } else if (j == nx - 1) {
-      const double Dlast = D0 - K * (double)sC[nx - 2];
-      e = -Dlast / dx + sRho[nx - 1] * dx / (2.0 * kEps0);
-    } else {
-      e = (K * (double)(sC[j - 1] + sC[j]) - 2.0 * D0) / (2.0 * dx);
-    }
-    a.E[j] = e;
-    if (!isfinite(e)) latch_error(a.ctl, kErrUnstable);
-  }
-}
+__global__ __launch_bounds__(kFieldThreads) void k_field(FieldArgs a) { field_block(a); }
 
 hipError_t launch_field(const FieldArgs& a, hipStream_t s) {
   if (a.nx > kMaxNx || a.nx < 3) return hipErrorInvalidValue;

@@ -32,6 +32,7 @@
 // parent-slot order.
 #include <climits>
 
+#include "field_block.h"
 #include "pic_internal.h"
 
 namespace pic {
@@ -120,8 +121,99 @@ __device__ __forceinline__ double cum_nu(const double* cum, int ntab, int p, dou
 // ---------------------------------------------------------------------------
 // k_decide
 
+#ifndef DECIDE_BLOCK
+#define DECIDE_BLOCK 512
+#endif
+constexpr int kDB = DECIDE_BLOCK;                // k_decide threads per workgroup
+constexpr int kDGroups = kTile / (4 * kDB);      // runs of four slots per thread per tile
+static_assert(kDGroups >= 1 && kTile % (4 * kDB) == 0, "a tile is whole runs of four slots");
+
+// The wall model and the collision decision of one pushed slot whose new
+// position is not a finite point inside the gap, or that is a collision
+// candidate: a small fraction of slots. x and vx are the pushed values and
+// are updated (reflection); the code, the number of own outputs and of
+// births are returned through c, o and b.
 template <int SP, bool MEASURE>
-__global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
+__device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long long* s_cnt,
+                                            int64_t slot, bool cand, double& x, double& vx,
+                                            uint32_t& c, uint32_t& o, uint32_t& b) {
+  const double L = a.L;
+  const uint32_t step = a.step;
+  bool alive = true;
+  uint32_t mul = 1;
+  if (!isfinite(x) || !isfinite(vx)) {
+    latch_error(a.ctl, kErrUnstable);
+    alive = false;
+    c |= 1u;
+  } else if (x < 0.0 || x > L) {
+    const double ub = u01(draw(step, (uint32_t)slot, SP, 0, a.seed, a.run).x);
+    if (SP == 0) {
+      if (ub < a.p_wall) {
+        x = (x < 0.0) ? -x : (L + L) - x;
+        vx = -vx;
+        if (x < 0.0 || x > L) {
+          alive = false;
+          c |= 4u;
+          atomicAdd(&s_cnt[C_REFLECT_LOST], 1ull);
+        } else {
+          c |= 2u;
+          atomicAdd(&s_cnt[C_E_REFLECTED], 1ull);
+        }
+      } else {
+        alive = false;
+        c |= 1u;
+        atomicAdd(&s_cnt[C_E_ABSORBED], 1ull);
+      }
+    } else {
+      alive = false;
+      atomicAdd(&s_cnt[C_I_ABSORBED], 1ull);
+      if (ub < a.p_wall) {
+        // a secondary electron leaves the wall the ion hit
+        c |= 3u;
+        b = 1;
+        atomicAdd(&s_cnt[C_SE_EMITTED], 1ull);
+        deposit_global(a.dep_other, x < 0.0 ? 0.0 : L, a.inv_dx, a.nx);
+      } else {
+        c |= 1u;
+      }
+    }
+  }
+  if (alive && cand) {
+    if (SP == 0) {
+      // electron candidate: the process at this speed decides whether a
+      // second electron and an ion are born
+      atomicAdd(&s_cnt[C_E_CAND], 1ull);
+      const uint32_t id = a.idin[slot];
+      const double vy = a.pvy[id], vz = a.pvz[id];
+      const double g2 = sqrt(vx * vx + vy * vy + vz * vz);
+      const double tv = g2 * a.inv_dv;
+      const double r = u01(draw(step, (uint32_t)slot, SP, 0, a.seed, a.run).z) * a.numax;
+      if (!(tv < (double)(a.ntab - 1))) atomicAdd(&s_cnt[C_BEYOND_TABLE], 1ull);
+      uint32_t proc = 1;
+      if (r < cum_nu(a.cum, a.ntab, 0, tv)) {
+        proc = 2;
+        atomicAdd(&s_cnt[C_E_ELASTIC], 1ull);
+      } else if (r < cum_nu(a.cum, a.ntab, 1, tv)) {
+        proc = 3;
+        atomicAdd(&s_cnt[C_E_EXC], 1ull);
+      } else if (r < cum_nu(a.cum, a.ntab, 2, tv)) {
+        proc = 4;
+        b = 1;
+        mul = 2;
+        atomicAdd(&s_cnt[C_E_ION], 1ull);
+        deposit_global(a.dep_other, x, a.inv_dx, a.nx);
+      }
+      c |= proc << 3;
+    } else {
+      atomicAdd(&s_cnt[C_I_CAND], 1ull);
+      c |= kIonPending;
+    }
+  }
+  o = alive ? mul : 0u;
+}
+
+template <int SP, bool MEASURE>
+__global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nx = a.nx;
   double* sE = reinterpret_cast<double*>(smem);
@@ -129,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
   double* sEW = reinterpret_cast<double*>(sH + nx);                 // MEASURE
   unsigned int* sEEPF = reinterpret_cast<unsigned int*>(sEW + nx);  // MEASURE
 
-  __shared__ uint32_t s_tot[3][kBlock / kWave];
+  __shared__ uint32_t s_tot[3][kDB / kWave];
   __shared__ int s_lo, s_hi;
   __shared__ unsigned long long s_cnt[NCOUNTERS];
 
@@ -139,13 +231,13 @@ __global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
   DevCtl* ctl = a.ctl;
   const int par = a.parity;
 
-  for (int j = tid; j < nx; j += kBlock) {
+  for (int j = tid; j < nx; j += kDB) {
     sE[j] = a.E[j];
     sH[j] = 0ull;
     if (MEASURE) sEW[j] = 0.0;
   }
   if (MEASURE)
-    for (int b = tid; b < a.nbins; b += kBlock) sEEPF[b] = 0u;
+    for (int b = tid; b < a.nbins; b += kDB) sEEPF[b] = 0u;
   if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
   if (tid == 0) {
     s_lo = INT_MAX;
@@ -172,16 +264,17 @@ __global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
   const uint32_t step = a.step;
   const double inv_dx = a.inv_dx;
   const double L = a.L;
+  const bool no_coll = a.no_coll != 0;
 
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t base = (int64_t)t * kTile;
     uint32_t own = 0, births = 0, rares = 0;
     int jlo = INT_MAX, jhi = -1;
-    // each thread takes runs of four consecutive slots (16-byte loads, one
-    // Philox block for the four candidacy draws, one 4-byte code store)
+    // each thread takes runs of four consecutive slots: 16-byte loads, one
+    // Philox block for the four candidacy draws, one 4-byte code store
 #pragma unroll
-    for (int g = 0; g < kPPT / 4; ++g) {
-      const int64_t s0 = base + (int64_t)g * (4 * kBlock) + 4 * tid;
+    for (int g = 0; g < kDGroups; ++g) {
+      const int64_t s0 = base + (int64_t)g * (4 * kDB) + 4 * tid;
       if (s0 >= n_tot) continue;
       const bool full = s0 + 3 < n_tot;
       double xs[4], vxs[4];
@@ -201,144 +294,94 @@ __global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
       uint4 rc = make_uint4(0u, 0u, 0u, 0u);
       if (s0 < n_push) rc = draw(step, (uint32_t)(s0 >> 2), SP, 4, a.seed, a.run);
       const uint32_t ucs[4] = {rc.x, rc.y, rc.z, rc.w};
-      uint32_t codes4 = 0;
-      // deposit of this run of slots, combined while they share a cell
-      int jr = -1;
-      unsigned long long h0 = 0, h1 = 0;
+
+      // push all four (no branches between them), then the few slots that
+      // left the gap or are candidates
+      uint32_t c[4], o[4], b[4];
+      bool need[4], cand[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t slot = s0 + q;
-        if (slot >= n_tot) break;
-        double x = xs[q], vx = vxs[q];
-        uint32_t c = 0, o = 1, b = 0, mul = 1;
-        if (slot < n_push) {
-          c = kCodePushed;
+        const bool in = slot < n_tot;
+        const bool pushed = slot < n_push;
+        c[q] = pushed ? (uint32_t)kCodePushed : 0u;
+        o[q] = in ? 1u : 0u;
+        b[q] = 0u;
+        cand[q] = false;
+        need[q] = false;
+        if (pushed) {
           int j;
           double f;
           int64_t w1;
-          cell_of(x, inv_dx, nx, j, f, w1);
-          double vy = 0.0, vz = 0.0;
+          cell_of(xs[q], inv_dx, nx, j, f, w1);
           if (MEASURE) {
             const uint32_t id = a.idin[slot];
-            vy = a.pvy[id];
-            vz = a.pvz[id];
-            const double eps = a.ek * (vx * vx + vy * vy + vz * vz);
+            const double vy = a.pvy[id], vz = a.pvz[id];
+            const double vx0 = vxs[q];
+            const double eps = a.ek * (vx0 * vx0 + vy * vy + vz * vz);
             atomicAdd(&sEW[j], ((double)(kOne32 - w1) * kInvTwo32) * eps);
             atomicAdd(&sEW[j + 1], ((double)w1 * kInvTwo32) * eps);
             jlo = min(jlo, j);
             jhi = max(jhi, j + 1);
-            if (fabs(x - a.half) <= a.eepf_hw) {
+            if (fabs(xs[q] - a.half) <= a.eepf_hw) {
               const int64_t bin = (int64_t)(eps * a.inv_de);
               if (bin >= 0 && bin < a.nbins) atomicAdd(&sEEPF[bin], 1u);
             }
           }
-          push(sE, j, f, a.acc, a.dts, x, vx);
-          bool alive = true;
-          if (!isfinite(x) || !isfinite(vx)) {
-            latch_error(ctl, kErrUnstable);
-            alive = false;
-            c |= 1u;
-          } else if (x < 0.0 || x > L) {
-            const double ub = u01(draw(step, (uint32_t)slot, SP, 0, a.seed, a.run).x);
-            if (SP == 0) {
-              if (ub < a.p_wall) {
-                x = (x < 0.0) ? -x : (L + L) - x;
-                vx = -vx;
-                if (x < 0.0 || x > L) {
-                  alive = false;
-                  c |= 4u;
-                  atomicAdd(&s_cnt[C_REFLECT_LOST], 1ull);
-                } else {
-                  c |= 2u;
-                  atomicAdd(&s_cnt[C_E_REFLECTED], 1ull);
-                }
-              } else {
-                alive = false;
-                c |= 1u;
-                atomicAdd(&s_cnt[C_E_ABSORBED], 1ull);
-              }
-            } else {
-              alive = false;
-              atomicAdd(&s_cnt[C_I_ABSORBED], 1ull);
-              if (ub < a.p_wall) {
-                // a secondary electron leaves the wall the ion hit
-                c |= 3u;
-                b = 1;
-                atomicAdd(&s_cnt[C_SE_EMITTED], 1ull);
-                deposit_global(a.dep_other, x < 0.0 ? 0.0 : L, inv_dx, nx);
-              } else {
-                c |= 1u;
-              }
-            }
-          }
-          if (alive && !a.no_coll && u01(ucs[q]) < a.pcoll) {
-            if (SP == 0) {
-              // electron candidate: the process at this speed decides
-              // whether a second electron and an ion are born
-              atomicAdd(&s_cnt[C_E_CAND], 1ull);
-              if (!MEASURE) {
-                const uint32_t id = a.idin[slot];
-                vy = a.pvy[id];
-                vz = a.pvz[id];
-              }
-              const double g2 = sqrt(vx * vx + vy * vy + vz * vz);
-              const double tv = g2 * a.inv_dv;
-              const double r = u01(draw(step, (uint32_t)slot, SP, 0, a.seed, a.run).z) * a.numax;
-              if (!(tv < (double)(a.ntab - 1))) atomicAdd(&s_cnt[C_BEYOND_TABLE], 1ull);
-              uint32_t proc = 1;
-              if (r < cum_nu(a.cum, a.ntab, 0, tv)) {
-                proc = 2;
-                atomicAdd(&s_cnt[C_E_ELASTIC], 1ull);
-              } else if (r < cum_nu(a.cum, a.ntab, 1, tv)) {
-                proc = 3;
-                atomicAdd(&s_cnt[C_E_EXC], 1ull);
-              } else if (r < cum_nu(a.cum, a.ntab, 2, tv)) {
-                proc = 4;
-                b = 1;
-                mul = 2;
-                atomicAdd(&s_cnt[C_E_ION], 1ull);
-                deposit_global(a.dep_other, x, inv_dx, nx);
-              }
-              c |= proc << 3;
-            } else {
-              atomicAdd(&s_cnt[C_I_CAND], 1ull);
-              c |= kIonPending;
-            }
-          }
-          o = alive ? mul : 0u;
+          push(sE, j, f, a.acc, a.dts, xs[q], vxs[q]);
+          cand[q] = !no_coll && u01(ucs[q]) < a.pcoll;
+          need[q] = cand[q] || !(xs[q] >= 0.0 && xs[q] <= L) || !isfinite(vxs[q]);
         }
-        if (o) {
-          // an ionization electron is born at its parent's position
-          int j;
-          double f;
-          int64_t w1;
-          cell_of(x, inv_dx, nx, j, f, w1);
-          if (j != jr) {
-            if (jr >= 0) {
-              atomicAdd(&sH[jr], h0);
-              atomicAdd(&sH[jr + 1], h1);
-            }
-            jr = j;
-            h0 = h1 = 0ull;
-            jlo = min(jlo, j);
-            jhi = max(jhi, j + 1);
-          }
-          h0 += (unsigned long long)o * (unsigned long long)(kOne32 - w1);
-          h1 += (unsigned long long)o * (unsigned long long)w1;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (need[q])
+          decide_rare<SP, MEASURE>(a, s_cnt, s0 + q, cand[q], xs[q], vxs[q], c[q], o[q], b[q]);
+
+      // deposit of the new positions (an ionization electron is born at its
+      // parent's position), combined when the four share a cell
+      int jq[4];
+      unsigned long long h0[4], h1[4];
+      int jr = -1;
+      bool same = true;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double f;
+        int64_t w1;
+        cell_of(xs[q], inv_dx, nx, jq[q], f, w1);
+        h0[q] = (unsigned long long)o[q] * (unsigned long long)(kOne32 - w1);
+        h1[q] = (unsigned long long)o[q] * (unsigned long long)w1;
+        if (o[q]) {
+          if (jr < 0) jr = jq[q];
+          same = same && jq[q] == jr;
+          jlo = min(jlo, jq[q]);
+          jhi = max(jhi, jq[q] + 1);
         }
-        codes4 |= c << (8 * q);
-        own += o;
-        births += b;
-        rares += outcome<SP>(c).rare ? 1u : 0u;
       }
       if (jr >= 0) {
-        atomicAdd(&sH[jr], h0);
-        atomicAdd(&sH[jr + 1], h1);
+        if (same) {
+          atomicAdd(&sH[jr], h0[0] + h0[1] + h0[2] + h0[3]);
+          atomicAdd(&sH[jr + 1], h1[0] + h1[1] + h1[2] + h1[3]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (o[q]) {
+              atomicAdd(&sH[jq[q]], h0[q]);
+              atomicAdd(&sH[jq[q] + 1], h1[q]);
+            }
+        }
       }
+      const uint32_t codes4 = c[0] | (c[1] << 8) | (c[2] << 16) | (c[3] << 24);
       if (full) {
         *reinterpret_cast<uint32_t*>(a.codes + s0) = codes4;
       } else {
-        for (int q = 0; q < 4 && s0 + q < n_tot; ++q) a.codes[s0 + q] = (uint8_t)(codes4 >> (8 * q));
+        for (int q = 0; q < 4 && s0 + q < n_tot; ++q) a.codes[s0 + q] = (uint8_t)c[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        own += o[q];
+        births += b[q];
+        rares += (s0 + q < n_tot && outcome<SP>(c[q]).rare) ? 1u : 0u;
       }
     }
 
@@ -358,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
     __syncthreads();
     if (tid == 0) {
       uint64_t o = 0, b = 0, r = 0;
-      for (int w = 0; w < kBlock / kWave; ++w) {
+      for (int w = 0; w < kDB / kWave; ++w) {
         o += s_tot[0][w];
         b += s_tot[1][w];
         r += s_tot[2][w];
@@ -366,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
       a.tcnt[t] = o | (b << 16) | (r << 32);
     }
     const int lo = s_lo, hi = s_hi;  // lo > hi when the tile deposited nothing
-    for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += kBlock) {
+    for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += kDB) {
       const unsigned long long v = sH[j];
       if (v) {
         atomicAdd(&a.dep_own[j], v);
@@ -390,7 +433,7 @@ __global__ __launch_bounds__(kBlock) void k_decide(PartArgs a) {
 
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
   if (MEASURE) {
-    for (int b = tid; b < a.nbins; b += kBlock)
+    for (int b = tid; b < a.nbins; b += kDB)
       if (sEEPF[b]) atomicAdd(&a.eepf[b], (unsigned long long)sEEPF[b]);
   }
 }
@@ -779,12 +822,54 @@ __global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
   const int64_t n = a.ctl->n_rare[SP];
   // births are appended after the other species' particles (as in k_emit)
   const int64_t bbase = SP == 0 ? a.ctl->n_i[a.parity] : a.ctl->e_out;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < n; i += (int64_t)gridDim.x * kBlock) {
+  // entries interleaved over the workgroups so that they spread over CUs
+  const int64_t nb = gridDim.x;
+  for (int64_t i = (int64_t)blockIdx.x + nb * tid; i < n; i += nb * kBlock) {
     const uint4 q = a.rq[i];
     rare_slot<SP>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
   }
   __syncthreads();
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
+}
+
+// ---------------------------------------------------------------------------
+// k_tail: the end of a step and the start of the next. Workgroup 0 solves
+// the next step's field (it needs only the deposits k_decide made); the
+// other workgroups take the queued slots of this step's last particle pass.
+// The two are independent: the field goes to the other E buffer, and the
+// queued slots read the E of this step.
+
+template <int SP>
+__global__ __launch_bounds__(kFieldThreads) void k_tail(FieldArgs f, PartArgs a) {
+  if (blockIdx.x == 0) {
+    field_block(f);
+    return;
+  }
+  __shared__ unsigned long long s_cnt[NCOUNTERS];
+  const int tid = threadIdx.x;
+  if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
+  __syncthreads();
+  const int64_t n = a.ctl->n_rare[SP];
+  const int64_t bbase = SP == 0 ? a.ctl->n_i[a.parity] : a.ctl->e_out;
+  // entries interleaved over the workgroups (one CU each) so that the few
+  // hundred to thousands of queued slots spread over many CUs
+  const int64_t nb = gridDim.x - 1;
+  for (int64_t i = (int64_t)(blockIdx.x - 1) + nb * tid; i < n; i += nb * kFieldThreads) {
+    const uint4 q = a.rq[i];
+    rare_slot<SP>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
+  }
+  __syncthreads();
+  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
+}
+
+hipError_t launch_tail(int species, const FieldArgs& f, const PartArgs& a, int rare_blocks,
+                       hipStream_t s) {
+  if (f.nx > kMaxNx || f.nx < 3 || rare_blocks < 1) return hipErrorInvalidValue;
+  if (species == 0)
+    hipLaunchKernelGGL((k_tail<0>), dim3(1 + rare_blocks), dim3(kFieldThreads), 0, s, f, a);
+  else
+    hipLaunchKernelGGL((k_tail<1>), dim3(1 + rare_blocks), dim3(kFieldThreads), 0, s, f, a);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -799,9 +884,9 @@ static size_t decide_lds(int nx, bool measure, int nbins) {
 static size_t emit_lds(int nx) { return (size_t)nx * 8; }
 
 template <typename K>
-static int blocks_per_cu(K kern, size_t lds) {
+static int blocks_per_cu(K kern, size_t lds, int threads = kBlock) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, lds) != hipSuccess || nb < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, lds) != hipSuccess || nb < 1)
     nb = 1;
   return nb;
 }
@@ -818,10 +903,10 @@ PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, in
     c.lds_decide[m] = decide_lds(nx, m == 1, nbins);
     int bpc;
     if (species == 0)
-      bpc = m ? blocks_per_cu(k_decide<0, true>, c.lds_decide[m])
-              : blocks_per_cu(k_decide<0, false>, c.lds_decide[m]);
+      bpc = m ? blocks_per_cu(k_decide<0, true>, c.lds_decide[m], kDB)
+              : blocks_per_cu(k_decide<0, false>, c.lds_decide[m], kDB);
     else
-      bpc = blocks_per_cu(k_decide<1, false>, c.lds_decide[m]);
+      bpc = blocks_per_cu(k_decide<1, false>, c.lds_decide[m], kDB);
     c.grid_decide[m] = clamp_grid((int64_t)bpc * num_cu, max_tiles);
   }
   c.lds_emit = emit_lds(nx);
@@ -837,13 +922,13 @@ hipError_t launch_particle_kernel(int kernel, int species, bool measure, const P
   const int m = (species == 0 && measure) ? 1 : 0;
   if (kernel == 0) {
     if (species == 1)
-      hipLaunchKernelGGL((k_decide<1, false>), dim3(c.grid_decide[0]), dim3(kBlock),
+      hipLaunchKernelGGL((k_decide<1, false>), dim3(c.grid_decide[0]), dim3(kDB),
                          c.lds_decide[0], s, a);
     else if (m)
-      hipLaunchKernelGGL((k_decide<0, true>), dim3(c.grid_decide[1]), dim3(kBlock),
+      hipLaunchKernelGGL((k_decide<0, true>), dim3(c.grid_decide[1]), dim3(kDB),
                          c.lds_decide[1], s, a);
     else
-      hipLaunchKernelGGL((k_decide<0, false>), dim3(c.grid_decide[0]), dim3(kBlock),
+      hipLaunchKernelGGL((k_decide<0, false>), dim3(c.grid_decide[0]), dim3(kDB),
                          c.lds_decide[0], s, a);
   } else if (kernel == 1) {
     if (species == 0)

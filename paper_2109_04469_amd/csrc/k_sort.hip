@@ -116,7 +116,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs a) {
     off[k] = a.cnt[(size_t)k * a.nblocks + blockIdx.x];
   __syncthreads();
   int64_t lo, hi;
-  chunk_range(min(uniform64(*a.count), a.cap), a.nblocks, blockIdx.x, lo, hi);
+  const int64_t n = min(uniform64(*a.count), a.cap);
+  // the rebuilt pool holds exactly the n sorted slots
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.pool_n = n;
+  chunk_range(n, a.nblocks, blockIdx.x, lo, hi);
   lo = uniform64(lo);
   hi = uniform64(hi);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
@@ -183,8 +186,6 @@ hipError_t launch_repack(const SortArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ void k_sort_pool_n(SortArgs a) { *a.pool_n = min(*a.count, a.cap); }
-
 hipError_t launch_sort(const SortArgs& a, hipStream_t s) {
   const size_t lds = (size_t)(a.nx - 1) * sizeof(uint32_t);
   hipLaunchKernelGGL(k_sort_count, dim3(a.nblocks), dim3(kSortThreads), lds, s, a);
@@ -192,7 +193,6 @@ hipError_t launch_sort(const SortArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanSegs), 0, s, a);
   hipLaunchKernelGGL(k_scan_down, dim3(kScanSegs), dim3(kSortThreads), 0, s, a);
   hipLaunchKernelGGL(k_sort_scatter, dim3(a.nblocks), dim3(kSortThreads), lds, s, a);
-  hipLaunchKernelGGL(k_sort_pool_n, dim3(1), dim3(1), 0, s, a);
   return hipGetLastError();
 }
 

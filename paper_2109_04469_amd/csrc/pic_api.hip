@@ -20,12 +20,13 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Velocity-pool entries per buffer: the live particles plus the entries of
 // particles absorbed and born since the last repack (every sort, or every
-// kRepackSteps steps without sorting).
-constexpr int kRepackSteps = 32;
-int64_t pool_capacity(int64_t cap) { return cap + (cap / 4 > 4096 ? cap / 4 : 4096); }
+// kRepackSteps steps when sorts are rarer). Running out latches
+// PIC_ECAPACITY.
+constexpr int kRepackSteps = 256;
+int64_t pool_capacity(int64_t cap) { return cap + (cap / 2 > 4096 ? cap / 2 : 4096); }
 
 struct Layout {
-  size_t ctl, part[2][2][2], pid[2][2], pool[2][2][2], codes[2], tcnt[2], rq[2], dep_e[2], dep_i[2], rho, phi, E, cum[2], th_cp,
+  size_t ctl, part[2][2][2], pid[2][2], pool[2][2][2], codes[2], tcnt[2], rq[2], dep_e[2], dep_i[2], rho, phi, E[2], cum[2], th_cp,
       th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, sort_cnt, sort_seg, total;
   int64_t max_tiles[2];
   int sort_blocks;
@@ -84,7 +85,7 @@ Layout make_layout(const pic_params* p, const pic_xsec* xs) {
   for (int b = 0; b < 2; ++b) L.dep_i[b] = take((size_t)nx * 8);
   L.rho = take((size_t)nx * 8);
   L.phi = take((size_t)nx * 8);
-  L.E = take((size_t)nx * 8);
+  for (int b = 0; b < 2; ++b) L.E[b] = take((size_t)nx * 8);
   L.cum[0] = take((size_t)3 * xs->n * 8);
   L.cum[1] = take((size_t)2 * xs->n * 8);
   L.th_cp = take((size_t)nx * 8);
@@ -193,7 +194,7 @@ PartArgs particle_args(pic_handle* h, int sp, int parity) {
   a.bpvy = h->pool[other][h->pcur[other]][0];
   a.bpvz = h->pool[other][h->pcur[other]][1];
   a.bpcap = h->pcap[other];
-  a.E = h->E;
+  a.E = h->Ebuf[parity];
   if (sp == 0) {
     a.dep_own = reinterpret_cast<unsigned long long*>(h->dep_e[parity ^ 1]);
     a.dep_other = reinterpret_cast<unsigned long long*>(h->dep_i[h->cur_hi]);
@@ -425,7 +426,8 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
   }
   h->rho = reinterpret_cast<double*>(w + L.rho);
   h->phi = reinterpret_cast<double*>(w + L.phi);
-  h->E = reinterpret_cast<double*>(w + L.E);
+  for (int b = 0; b < 2; ++b) h->Ebuf[b] = reinterpret_cast<double*>(w + L.E[b]);
+  h->e_last = 0;
   h->th_cp = reinterpret_cast<double*>(w + L.th_cp);
   h->th_m = reinterpret_cast<double*>(w + L.th_m);
   h->acc_ne = reinterpret_cast<double*>(w + L.acc_ne);
@@ -553,85 +555,124 @@ int pic_get_state(pic_handle* h, int species, double* x, double* vx, double* vy,
   return PIC_OK;
 }
 
-// One species' particle pass: decide, emit and rare kernels, each timed on
-// its own and the three together.
-int particle_pass(pic_handle* h, int sp, const PartArgs& a) {
-  static const int kTimer[2][3] = {{PIC_TIMER_E_DECIDE, PIC_TIMER_E_EMIT, PIC_TIMER_E_RARE},
-                                   {PIC_TIMER_I_DECIDE, PIC_TIMER_I_EMIT, PIC_TIMER_I_RARE}};
-  const bool measure = sp == 0 && h->measuring;
-  const int pass = timer_begin(h);
-  for (int k = 0; k < 3; ++k) {
-    const int ev = h->timing >= 2 ? timer_begin(h) : -1;
-    HIP_TRY(launch_particle_kernel(k, sp, measure, a, h->launch[sp], h->stream));
-    timer_end(h, kTimer[sp][k], ev);
-  }
-  timer_end(h, sp == 0 ? PIC_TIMER_ELECTRON : PIC_TIMER_ION, pass);
-  return PIC_OK;
+FieldArgs field_args(pic_handle* h, int field_mode_, bool ion_step) {
+  const int par = (int)(h->step & 1);
+  FieldArgs f{};
+  f.dep_e = h->dep_e[par];
+  f.dep_i = h->dep_i[h->cur_hi];
+  f.zero_a = h->dep_e[par ^ 1];
+  f.zero_b = ion_step ? h->dep_i[1 - h->cur_hi] : nullptr;
+  f.rho = h->rho;
+  f.phi = h->phi;
+  f.E = h->Ebuf[par];
+  f.th_cp = h->th_cp;
+  f.th_m = h->th_m;
+  f.acc_ne = h->acc_ne;
+  f.acc_ni = h->acc_ni;
+  f.acc_w = h->acc_w;
+  f.ctl = h->ctl;
+  f.V = h->vtab[(size_t)(h->step % h->p.steps_per_cycle)];
+  f.dx = h->dx;
+  f.qfac32 = h->qfac32;
+  f.nfac32 = h->nfac32;
+  f.kpois = h->kpois;
+  f.nx = h->nx;
+  f.mode = field_mode_;
+  f.measuring = h->measuring;
+  f.parity = par;
+  return f;
 }
 
+bool is_ion_step(const pic_handle* h, int64_t step) {
+  return !(h->p.flags & PIC_FLAG_IMMOBILE_IONS) && (step % h->p.ion_subcycle == 0);
+}
+
+constexpr int kTailRareBlocks = 128;
+
+// One step. Launch order on the handle's stream:
+//   [field(n)]  e_decide e_emit  (e_rare i_decide i_emit on ion steps)
+//   then either tail(rare of the last pass + field(n+1)) when another step
+//   follows in this call, or the last pass's rare kernel alone.
+// A sort or repack of the particle arrays, when due, comes after that.
 int pic_step(pic_handle* h, int64_t n_steps) {
   if (!h || n_steps < 0) return PIC_EINVAL;
   if ((h->p.flags & PIC_FLAG_FIXED_E) && !h->field_fixed_set) return PIC_ESTATE;
   const pic_params& p = h->p;
   const int mode = field_mode(h);
+  bool field_ready = false;  // field of h->step already enqueued by a tail
   for (int64_t it = 0; it < n_steps; ++it) {
     const int par = (int)(h->step & 1);
-    const bool ion_step =
-        !(p.flags & PIC_FLAG_IMMOBILE_IONS) && (h->step % p.ion_subcycle == 0);
-    FieldArgs f{};
-    f.dep_e = h->dep_e[par];
-    f.dep_i = h->dep_i[h->cur_hi];
-    f.zero_a = h->dep_e[par ^ 1];
-    f.zero_b = ion_step ? h->dep_i[1 - h->cur_hi] : nullptr;
-    f.rho = h->rho;
-    f.phi = h->phi;
-    f.E = h->E;
-    f.th_cp = h->th_cp;
-    f.th_m = h->th_m;
-    f.acc_ne = h->acc_ne;
-    f.acc_ni = h->acc_ni;
-    f.acc_w = h->acc_w;
-    f.ctl = h->ctl;
-    f.V = h->vtab[(size_t)(h->step % p.steps_per_cycle)];
-    f.dx = h->dx;
-    f.qfac32 = h->qfac32;
-    f.nfac32 = h->nfac32;
-    f.kpois = h->kpois;
-    f.nx = h->nx;
-    f.mode = mode;
-    f.measuring = h->measuring;
-    f.parity = par;
-    int ev = timer_begin(h);
-    HIP_TRY(launch_field(f, h->stream));
-    timer_end(h, PIC_TIMER_FIELD, ev);
+    const bool ion_step = is_ion_step(h, h->step);
+    if (!field_ready) {
+      const int ev = timer_begin(h);
+      HIP_TRY(launch_field(field_args(h, mode, ion_step), h->stream));
+      timer_end(h, PIC_TIMER_FIELD, ev);
+    }
+    h->e_last = par;
+    const bool measure = h->measuring != 0;
 
-    PartArgs ae = particle_args(h, 0, par);
-    int st = particle_pass(h, 0, ae);
-    if (st) return st;
+    // electron pass
+    const PartArgs ae = particle_args(h, 0, par);
+    const int e_pass = timer_begin(h);
+    for (int k = 0; k < 2; ++k) {
+      const int ev = h->timing >= 2 ? timer_begin(h) : -1;
+      HIP_TRY(launch_particle_kernel(k, 0, measure, ae, h->launch[0], h->stream));
+      timer_end(h, k == 0 ? PIC_TIMER_E_DECIDE : PIC_TIMER_E_EMIT, ev);
+    }
     h->cur[0] ^= 1;
+    int pend_sp = 0, pend_pass = e_pass;
+    PartArgs pend = ae;
     if (ion_step) {
-      PartArgs ai = particle_args(h, 1, par);
-      st = particle_pass(h, 1, ai);
-      if (st) return st;
+      // the ions take this step's ionization ions with their velocities
+      const int ev = h->timing >= 2 ? timer_begin(h) : -1;
+      HIP_TRY(launch_particle_kernel(2, 0, measure, ae, h->launch[0], h->stream));
+      timer_end(h, PIC_TIMER_E_RARE, ev);
+      timer_end(h, PIC_TIMER_ELECTRON, e_pass);
+      const PartArgs ai = particle_args(h, 1, par);
+      const int i_pass = timer_begin(h);
+      for (int k = 0; k < 2; ++k) {
+        const int ev2 = h->timing >= 2 ? timer_begin(h) : -1;
+        HIP_TRY(launch_particle_kernel(k, 1, false, ai, h->launch[1], h->stream));
+        timer_end(h, k == 0 ? PIC_TIMER_I_DECIDE : PIC_TIMER_I_EMIT, ev2);
+      }
       h->cur[1] ^= 1;
       h->cur_hi ^= 1;
+      pend_sp = 1;
+      pend_pass = i_pass;
+      pend = ai;
     }
     h->step += 1;
-    // keep the event backlog bounded
-    if (h->ev_used.size() >= 4096) {
-      const int st = timer_collect(h);
-      if (st) return st;
+
+    // the last pass's queued slots, with the next step's field if one follows
+    const int rare_timer = pend_sp == 0 ? PIC_TIMER_E_RARE : PIC_TIMER_I_RARE;
+    const int ev = h->timing >= 2 ? timer_begin(h) : -1;
+    if (it + 1 < n_steps) {
+      HIP_TRY(launch_tail(pend_sp, field_args(h, mode, is_ion_step(h, h->step)), pend,
+                          kTailRareBlocks, h->stream));
+      field_ready = true;
+    } else {
+      HIP_TRY(launch_particle_kernel(2, pend_sp, measure, pend, h->launch[pend_sp], h->stream));
+      field_ready = false;
     }
+    timer_end(h, rare_timer, ev);
+    timer_end(h, pend_sp == 0 ? PIC_TIMER_ELECTRON : PIC_TIMER_ION, pend_pass);
+
     if (p.sort_interval > 0 && h->step % p.sort_interval == 0) {
       int s = sort_species(h, 0);
       if (s) return s;
       s = sort_species(h, 1);
       if (s) return s;
-    } else if (h->step % kRepackSteps == 0) {
+    } else if ((p.sort_interval == 0 || p.sort_interval > kRepackSteps) &&
+               h->step % kRepackSteps == 0) {
       int s = repack_species(h, 0);
       if (s) return s;
       s = repack_species(h, 1);
       if (s) return s;
+    }
+    // keep the event backlog bounded
+    if (h->ev_used.size() >= 4096) {
+      const int st = timer_collect(h);
+      if (st) return st;
     }
   }
   return PIC_OK;
@@ -645,7 +686,8 @@ int pic_sync(pic_handle* h) {
 int pic_set_field(pic_handle* h, const double* E) {
   if (!h || !E) return PIC_EINVAL;
   if (!(h->p.flags & PIC_FLAG_FIXED_E)) return PIC_ESTATE;
-  HIP_TRY(hipMemcpyAsync(h->E, E, (size_t)h->nx * 8, hipMemcpyDefault, h->stream));
+  for (int b = 0; b < 2; ++b)
+    HIP_TRY(hipMemcpyAsync(h->Ebuf[b], E, (size_t)h->nx * 8, hipMemcpyDefault, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->field_fixed_set = 1;
   return PIC_OK;
@@ -658,7 +700,7 @@ int pic_get_field(pic_handle* h, double* rho, double* phi, double* E, int64_t* d
   const int par = (int)(h->step & 1);
   if (rho) HIP_TRY(hipMemcpyAsync(rho, h->rho, b, hipMemcpyDefault, h->stream));
   if (phi) HIP_TRY(hipMemcpyAsync(phi, h->phi, b, hipMemcpyDefault, h->stream));
-  if (E) HIP_TRY(hipMemcpyAsync(E, h->E, b, hipMemcpyDefault, h->stream));
+  if (E) HIP_TRY(hipMemcpyAsync(E, h->Ebuf[h->e_last], b, hipMemcpyDefault, h->stream));
   if (deposit_e) HIP_TRY(hipMemcpyAsync(deposit_e, h->dep_e[par], b, hipMemcpyDefault, h->stream));
   if (deposit_i)
     HIP_TRY(hipMemcpyAsync(deposit_i, h->dep_i[h->cur_hi], b, hipMemcpyDefault, h->stream));

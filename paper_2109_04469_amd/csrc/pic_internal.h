@@ -144,6 +144,10 @@ PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, in
 // kernel 0: k_decide, 1: k_emit, 2: k_rare (launched in this order)
 hipError_t launch_particle_kernel(int kernel, int species, bool measure, const PartArgs& a,
                                   const PartLaunch& c, hipStream_t s);
+// field of the next step (one workgroup) together with the queued slots of
+// this step's last particle pass of `species` (rare_blocks workgroups)
+hipError_t launch_tail(int species, const FieldArgs& f, const PartArgs& a, int rare_blocks,
+                       hipStream_t s);
 hipError_t launch_sort(const SortArgs& a, hipStream_t s);
 // pool repacked in slot order (no reordering of the slots)
 hipError_t launch_repack(const SortArgs& a, hipStream_t s);
@@ -191,7 +195,8 @@ struct pic_handle {
   int64_t* dep_i[2];
   double* rho;
   double* phi;
-  double* E;
+  double* Ebuf[2];  // E of even and odd steps
+  int e_last;       // buffer of the last field solved
   double* cum[2];
   double* th_cp;
   double* th_m;
