@@ -265,6 +265,7 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
   const double inv_dx = a.inv_dx;
   const double L = a.L;
   const bool no_coll = a.no_coll != 0;
+  const uint64_t cand_thr = no_coll ? 0ull : a.pcoll_thr;
 
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t base = (int64_t)t * kTile;
@@ -295,8 +296,8 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
       if (s0 < n_push) rc = draw(step, (uint32_t)(s0 >> 2), SP, 4, a.seed, a.run);
       const uint32_t ucs[4] = {rc.x, rc.y, rc.z, rc.w};
 
-      // push all four (no branches between them), then the few slots that
-      // left the gap or are candidates
+      // push all four, then the few slots that left the gap or are
+      // candidates
       uint32_t c[4], o[4], b[4];
       bool need[4], cand[4];
 #pragma unroll
@@ -329,7 +330,8 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
             }
           }
           push(sE, j, f, a.acc, a.dts, xs[q], vxs[q]);
-          cand[q] = !no_coll && u01(ucs[q]) < a.pcoll;
+          // u01(r) < pcoll, decided exactly on the integer word
+          cand[q] = (uint64_t)ucs[q] < cand_thr;
           need[q] = cand[q] || !(xs[q] >= 0.0 && xs[q] <= L) || !isfinite(vxs[q]);
         }
       }

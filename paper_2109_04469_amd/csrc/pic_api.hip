@@ -106,6 +106,16 @@ Layout make_layout(const pic_params* p, const pic_xsec* xs) {
   return L;
 }
 
+// u01(r) = (r + 1/2) 2^-32 is exact in FP64, so u01(r) < p holds exactly
+// when r + 1/2 < P = p 2^32 (scaling by a power of two is exact), i.e. for
+// integers r < ceil(P - 1/2); P - 1/2 is exact for P < 2^32.
+uint64_t candidacy_threshold(double p) {
+  if (!(p > 0.0)) return 0;
+  if (p >= 1.0) return (uint64_t)1 << 32;
+  const double t = std::ceil(std::ldexp(p, 32) - 0.5);
+  return t <= 0.0 ? 0 : (uint64_t)t;
+}
+
 int hip_status(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EHIP; }
 
 #define HIP_TRY(expr)                        \
@@ -218,6 +228,7 @@ PartArgs particle_args(pic_handle* h, int sp, int parity) {
   a.dts = h->dts[sp];
   a.p_wall = sp == 0 ? h->p.reflection : h->p.gamma_see;
   a.pcoll = h->pcoll[sp];
+  a.pcoll_thr = candidacy_threshold(h->pcoll[sp]);
   a.numax = h->numax[sp];
   a.inv_dv = h->inv_dv[sp];
   a.mr = h->mr_e;

@@ -85,6 +85,7 @@ struct PartArgs {
   double dts;
   double p_wall;   // R (electrons) or gamma (ions)
   double pcoll;
+  uint64_t pcoll_thr;  // u01(r) < pcoll exactly when r < pcoll_thr (r a 32-bit word)
   double numax;
   double inv_dv;
   double mr;       // m/(m+M) (electron elastic)
