@@ -237,3 +237,111 @@ def test_determinism_and_exact_resume():
     for sp in (0, 1):
         assert_state_equal(a[sp], b[sp], what="rerun")
         assert_state_equal(a[sp], c[sp], what="resume")
+
+
+def test_full_size_c3_steps_match_oracle():
+    # The large workload at its full size (4M electrons + 4M ions, 2049
+    # nodes) in the library's default launch configuration, the one bench.py
+    # times, with the default solver. The oracle runs the same steps (about a
+    # second each on one core); every decision, count and counter must agree
+    # and states within rounding. Step 0 moves both species (ion
+    # sub-cycling x10), steps 1-2 the electrons; a cell sort after step 2.
+    w = workloads.get("c3_large_lowp")
+    p = dict(w["params"], flags=RECORD, sort_interval=2)
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w)
+    gpu, ora = pair(p, xs, init)
+    L = p["gap_m"]
+    for k in range(3):
+        gpu.step(1)
+        assert ora.step(1) == 0
+        for sp, vs in ((0, _vth(2.0, ME)), (1, _vth(0.03, MAR))):
+            dg, do = gpu.decisions(sp), ora.decisions(sp)
+            assert dg.size == do.size, (k, sp)
+            assert np.array_equal(dg, do), f"step {k} species {sp}: decisions"
+            assert_state_close(gpu.get_state(sp), ora.get_state(sp), L, vs, rtol=1e-10,
+                               what=f"step {k} species {sp}")
+        assert np.array_equal(gpu.counters(), ora.counters()), f"step {k}"
+    # the integer deposit of the GPU's own positions is exact at any size;
+    # against the oracle's positions (other Poisson solver, rounding-level
+    # differences) only a few fixed-point weights may move by one unit
+    import oracle as O
+
+    f = gpu.get_field()
+    o = ora.deposit() or ora.get_field()
+    nx = p["n_cells"] + 1
+    inv_dx = 1.0 / (L / p["n_cells"])  # as both sides compute it
+    for sp, key in ((0, "dep_e"), (1, "dep_i")):
+        xg = gpu.get_state(sp)[0]
+        assert np.array_equal(f[key], O.deposit_array(nx, inv_dx, xg)), key
+        assert np.max(np.abs(f[key] - o[key])) <= 64, key
+
+
+def test_measured_moments_match_oracle():
+    # Time-averaged densities, CIC mean energy and the mid-gap EEPF over 30
+    # measured steps (Sec. 3): the histogram counts are integers and must be
+    # equal; the FP64 sums agree to rounding.
+    w = workloads.scaled(workloads.get("c1_small"), 8000)
+    p = dict(w["params"], flags=THOMAS, reflection=0.2, gamma_see=0.1)
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w, seed=12)
+    gpu, ora = pair(p, xs, init)
+    gpu.step(20)
+    assert ora.step(20) == 0
+    gpu.measure(True)
+    ora.measure(True)
+    gpu.step(30)
+    assert ora.step(30) == 0
+    mg, mo = gpu.moments(), ora.moments()
+    assert mg["steps"] == mo["steps"] == 30
+    for k in ("n_e", "n_i", "mean_energy_e", "eepf"):
+        g, o = mg[k], mo[k]
+        scale = max(np.max(np.abs(o)), 1e-300)
+        assert np.max(np.abs(g - o)) <= 1e-9 * scale, k
+    assert np.sum(mg["eepf"] > 0) == np.sum(mo["eepf"] > 0)
+
+
+def test_capacity_overflow_is_reported():
+    # Births beyond the output capacity are an error, not a silent drop:
+    # 50 eV electrons at 300 Pa ionize in the first step, and the electron
+    # arrays have no room beyond the initial count.
+    w = workloads.scaled(workloads.get("c1_small"), 2000)
+    p = dict(w["params"], capacity=(2000, 4000), pressure_pa=300.0)
+    xs = xsec.argon_synthetic()
+    L = p["gap_m"]
+    e = state.maxwellian_uniform(2000, L, 50.0, 0, 3)
+    i = state.maxwellian_uniform(2000, L, 0.03, 1, 3)
+    from paper_2109_04469_amd import Discharge
+
+    d = Discharge(p, xs)
+    d.set_state(0, *e, step=0)
+    d.set_state(1, *i, step=0)
+    d.step(1)
+    assert d.sync() == -3
+
+
+def test_timing_levels():
+    w = workloads.scaled(workloads.get("c1_small"), 4000)
+    p = dict(w["params"], ion_subcycle=5)
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w, seed=2)
+    from paper_2109_04469_amd import Discharge, PicError
+
+    d = Discharge(p, xs)
+    for sp in (0, 1):
+        d.set_state(sp, *init[sp], step=0)
+    with pytest.raises(PicError):
+        d.timing(3)
+    d.timing(1)
+    d.step(10)
+    t = d.get_timing(reset=True)
+    assert t["electron"][1] == 10 and t["ion"][1] == 2 and t["field"][1] == 1
+    assert t["e_decide"][1] == 0
+    d.timing(2)
+    d.step(10)
+    t = d.get_timing(reset=True)
+    assert t["e_decide"][1] == 10 and t["e_emit"][1] == 10 and t["i_decide"][1] == 2
+    assert all(v[0] > 0 for k, v in t.items() if v[1])
+    d.timing(0)
+    d.step(5)
+    assert all(v[1] == 0 for v in d.get_timing().values())
