@@ -38,6 +38,11 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/s (push+MCC+CIC) vs HBM roofline; batched & warm-start speedup"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE_STEP = 64
+# HBM bytes the electron pass moves per electron particle-step, read with
+# rocprofv3 FETCH_SIZE (x2, the factor a plain copy of known size gives)
+# and WRITE_SIZE (x1) at c3; to be re-measured whenever the pass's kernels
+# change (None when not measured for the current kernels)
+PASS_TRAFFIC_BYTES_PER_PARTICLE = 59.65
 
 DESCRIPTIONS = {
     "c3_large_lowp": ("gap 6.7 cm, 2048 cells, dt=T_RF/8000, 13.56 MHz, 500 V, 2 Pa, gamma 0.2, R 0.5, "
@@ -187,8 +192,11 @@ def main():
             avg_s = ems / en * 1e-3
             bytes_per_launch = BYTES_PER_PARTICLE_STEP * pe_w / en
             achieved = bytes_per_launch / avg_s / 1e9
+            traffic = (PASS_TRAFFIC_BYTES_PER_PARTICLE * pe_w / en
+                       if PASS_TRAFFIC_BYTES_PER_PARTICLE is not None else None)
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
                     "kernel": ("electron particle pass: k_decide<0> + k_emit<0> + k_tail<0> "
                                "(its queued slots, overlapped with the next step's field); "
                                "k_rare<0> instead of k_tail on ion steps"),
