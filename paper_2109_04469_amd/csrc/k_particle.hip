@@ -477,24 +477,16 @@ __device__ __forceinline__ void reload(const PartArgs& a, const double* E, int64
   repush(a, E, c, x, vx);
 }
 
-// slots per thread whose loads are in flight together
-#ifndef EMIT_GROUP
-#define EMIT_GROUP 4
-#endif
-constexpr int kEmitGroup = EMIT_GROUP;
-#ifndef EMIT_EARLY
-#define EMIT_EARLY 0
-#endif
-// groups whose loads are issued before the tile scan
-constexpr int kEmitEarly = EMIT_EARLY;
-static_assert(kPPT * (kBlock / kWave) <= kWave, "one wave scans the segment totals");
+// pairs of consecutive slots per lane and tile in k_emit
+constexpr int kEPairs = kPPT / 2;
+static_assert(kPPT % 2 == 0, "k_emit takes pairs of slots");
 
 template <int SP>
 __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* sE = reinterpret_cast<double*>(smem);
-  __shared__ uint32_t s_wtot[kPPT][kBlock / kWave];
-  __shared__ uint32_t s_woff[kPPT][kBlock / kWave];
+  __shared__ uint32_t s_wtot[kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_woff[kEPairs][kBlock / kWave];
   __shared__ uint64_t s_red[3][kBlock / kWave];
   __shared__ uint32_t s_agg, s_qn;
 
@@ -560,83 +552,96 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
 
   for (int t = t0; t < t1; ++t) {
     const int64_t base = (int64_t)t * kTile;
-    uint32_t code[kPPT], loc[kPPT];
+    // pairs of consecutive slots per lane: 16-byte loads of x and v_x, an
+    // 8-byte load of the two pool indices, one 2-byte load of the codes; all
+    // loads are issued before the tile's scan
+    uint32_t code[kPPT], loc[kEPairs];
     double px[kPPT], pvx[kPPT];
     uint32_t pid[kPPT];
 #pragma unroll
-    for (int k = 0; k < kPPT; ++k) {
-      const int64_t slot = base + k * kBlock + tid;
-      uint32_t c = 0, cnt = 0;
-      px[k] = pvx[k] = 0.0;
-      pid[k] = 0u;
-      if (slot < n_tot) {
-        c = a.codes[slot];
-        const Outcome oc = outcome<SP>(c);
-        cnt = oc.own | (oc.birth << 16);
-        c |= 0x100u;  // slot in range
-        if (k < kEmitEarly * kEmitGroup) {
-          // these loads do not wait for the scan
-          px[k] = a.xin[slot];
-          pvx[k] = a.vxin[slot];
-          pid[k] = a.idin[slot];
+    for (int k = 0; k < kEPairs; ++k) {
+      const int64_t s0 = base + k * (2 * kBlock) + 2 * tid;
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        code[2 * k + h] = 0;
+        px[2 * k + h] = pvx[2 * k + h] = 0.0;
+        pid[2 * k + h] = 0u;
+      }
+      if (s0 + 1 < n_tot) {
+        const uint32_t c2 = *reinterpret_cast<const uint16_t*>(a.codes + s0);
+        const double2 xx = *reinterpret_cast<const double2*>(a.xin + s0);
+        const double2 vv = *reinterpret_cast<const double2*>(a.vxin + s0);
+        const uint2 ii = *reinterpret_cast<const uint2*>(a.idin + s0);
+        code[2 * k] = (c2 & 0xFFu) | 0x100u;
+        code[2 * k + 1] = (c2 >> 8) | 0x100u;
+        px[2 * k] = xx.x;
+        px[2 * k + 1] = xx.y;
+        pvx[2 * k] = vv.x;
+        pvx[2 * k + 1] = vv.y;
+        pid[2 * k] = ii.x;
+        pid[2 * k + 1] = ii.y;
+      } else if (s0 < n_tot) {
+        code[2 * k] = (uint32_t)a.codes[s0] | 0x100u;
+        px[2 * k] = a.xin[s0];
+        pvx[2 * k] = a.vxin[s0];
+        pid[2 * k] = a.idin[s0];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t c = code[2 * k + h];
+        if (c & 0x100u) {
+          const Outcome oc = outcome<SP>(c);
+          cnt += oc.own | (oc.birth << 16);
         }
       }
-      code[k] = c;
       const uint32_t inc = wave_incl_scan<unsigned int>(cnt);
       loc[k] = inc - cnt;
       if (lane == kWave - 1) s_wtot[k][wave] = inc;
     }
     __syncthreads();
     if (wave == 0) {
-      // offsets of the (k, wave) segments, k-major: kPPT * 4 <= 64 values
+      // offsets of the (pair row, wave) segments, row-major
       const uint32_t* wt = &s_wtot[0][0];
       uint32_t* wo = &s_woff[0][0];
-      const uint32_t v = lane < kPPT * (kBlock / kWave) ? wt[lane] : 0u;
+      constexpr int nseg = kEPairs * (kBlock / kWave);
+      const uint32_t v = lane < nseg ? wt[lane] : 0u;
       const uint32_t inc = wave_incl_scan<unsigned int>(v);
-      if (lane < kPPT * (kBlock / kWave)) wo[lane] = inc - v;
-      if (lane == kPPT * (kBlock / kWave) - 1) s_agg = inc;
+      if (lane < nseg) wo[lane] = inc - v;
+      if (lane == nseg - 1) s_agg = inc;
     }
     __syncthreads();
 
 #pragma unroll
-    for (int g = 0; g < kPPT; g += kEmitGroup) {
-      if (g >= kEmitEarly * kEmitGroup) {
+    for (int k = 0; k < kEPairs; ++k) {
+      uint32_t off = s_woff[k][wave] + loc[k];
 #pragma unroll
-        for (int q = 0; q < kEmitGroup; ++q) {
-          const int64_t slot = base + (g + q) * kBlock + tid;
-          if (code[g + q] & 0x100u) {
-            px[g + q] = a.xin[slot];
-            pvx[g + q] = a.vxin[slot];
-            pid[g + q] = a.idin[slot];
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kEmitGroup; ++q) {
-        const int k = g + q;
-        const uint32_t c = code[k];
-        const Outcome oc = outcome<SP>(c);
+      for (int h = 0; h < 2; ++h) {
+        const int q = 2 * k + h;
+        const uint32_t c = code[q];
         const bool in = (c & 0x100u) != 0;
-        const uint32_t off = s_woff[k][wave] + loc[k];
+        const Outcome oc = outcome<SP>(c);
         const bool rare = in && oc.rare;
+        const int64_t slot = base + k * (2 * kBlock) + 2 * tid + h;
         const uint64_t m = __ballot(rare);
         if (m) {
-          // queue the slot for k_rare with its output slots
+          // queue the slot for the rare work with its output slots
           uint32_t qb = 0;
           if (lane == 0) qb = atomicAdd(&s_qn, (uint32_t)__popcll(m));
           qb = __shfl(qb, 0);
           if (rare) {
             const int64_t pos = prefR + qb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            a.rq[pos] = make_uint4((uint32_t)(base + k * kBlock + tid), c & 0xFFu,
-                                   (uint32_t)(prefO + (off & 0xFFFFu)),
+            a.rq[pos] = make_uint4((uint32_t)slot, c & 0xFFu, (uint32_t)(prefO + (off & 0xFFFFu)),
                                    (uint32_t)(prefB + (off >> 16)));
           }
         }
-        if (!in || rare || !oc.own) continue;
-        const int64_t dest = prefO + (int64_t)(off & 0xFFFFu);
-        double x = px[k], vx = pvx[k];
-        repush(a, sE, c, x, vx);
-        if (dest < a.cap) store3(a, dest, x, vx, pid[k]);
+        if (in && !rare && oc.own) {
+          const int64_t dest = prefO + (int64_t)(off & 0xFFFFu);
+          double x = px[q], vx = pvx[q];
+          repush(a, sE, c, x, vx);
+          if (dest < a.cap) store3(a, dest, x, vx, pid[q]);
+        }
+        if (in) off += oc.own | (oc.birth << 16);
       }
     }
     __syncthreads();
