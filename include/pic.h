@@ -228,6 +228,16 @@ int pic_get_counters(pic_handle* h, int64_t* counters);
  * *n receives the number of slots. Synchronises. */
 int pic_get_decisions(pic_handle* h, int species, uint8_t* codes, int64_t cap, int64_t* n);
 
+/* Advances n independent discharges by n_steps each. Each handle's steps
+ * are enqueued on its own stream (the one given to pic_init) in chunks of
+ * `chunk` steps (chunk >= 1), round robin over the handles, so that
+ * discharges on different streams run concurrently on the GPU: a parameter
+ * sweep of the kind of Sec. 3 (N_t, N_x, W, R, gamma, pressure, voltage)
+ * advanced as one batch. Every discharge computes exactly what pic_step on
+ * it alone computes. Does not synchronise; errors of one handle stop the
+ * enqueueing and are returned. Handles must be distinct. */
+int pic_step_many(pic_handle* const* handles, int n, int64_t n_steps, int64_t chunk);
+
 /* Kernel timing with HIP events recorded on the handle's stream
  * (measurement surface). level 0: off. level 1: two event records around
  * the field kernel, each species' particle pass (PIC_TIMER_ELECTRON,

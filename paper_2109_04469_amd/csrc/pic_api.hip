@@ -689,6 +689,23 @@ int pic_step(pic_handle* h, int64_t n_steps) {
   return PIC_OK;
 }
 
+int pic_step_many(pic_handle* const* handles, int n, int64_t n_steps, int64_t chunk) {
+  if (n < 0 || n_steps < 0 || chunk < 1 || (n > 0 && !handles)) return PIC_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!handles[i]) return PIC_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (handles[k] == handles[i]) return PIC_EINVAL;
+  }
+  for (int64_t done = 0; done < n_steps; done += chunk) {
+    const int64_t m = (n_steps - done < chunk) ? n_steps - done : chunk;
+    for (int i = 0; i < n; ++i) {
+      const int st = pic_step(handles[i], m);
+      if (st) return st;
+    }
+  }
+  return PIC_OK;
+}
+
 int pic_sync(pic_handle* h) {
   if (!h) return PIC_EINVAL;
   return latched(h);

@@ -56,7 +56,7 @@ def _ptr(a):
 class Discharge:
     """One RF discharge on one GPU (libpic handle + its torch workspace)."""
 
-    def __init__(self, params: dict, xs, device="cuda:0"):
+    def __init__(self, params: dict, xs, device="cuda:0", stream=None):
         self.L = capi.load()
         self.device = torch.device(device)
         self.params = dict(params)
@@ -68,7 +68,8 @@ class Discharge:
         self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         off = (-base) % 256
-        self.stream = torch.cuda.current_stream(self.device)
+        # the library enqueues all of this discharge's work on this stream
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         check(self.L.pic_init(ctypes.byref(self._p), ctypes.byref(self._x), ctypes.c_void_p(base + off),
                               nbytes.value, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
@@ -220,3 +221,11 @@ def selftest_copy(src: "torch.Tensor", dst: "torch.Tensor"):
     s = torch.cuda.current_stream(src.device)
     check(L.pic_selftest_copy(_ptr(src), _ptr(dst), src.numel(), ctypes.c_void_p(s.cuda_stream)),
           "selftest_copy")
+
+
+def step_many(discharges, n_steps, chunk=50):
+    """Advances independent discharges (each on its own stream) by n_steps
+    each, interleaved so that they run concurrently; does not synchronise."""
+    L = capi.load()
+    arr = (ctypes.c_void_p * len(discharges))(*[d.h.value for d in discharges])
+    check(L.pic_step_many(arr, len(discharges), int(n_steps), int(chunk)), "pic_step_many")

@@ -396,3 +396,33 @@ def test_statistical_parity_8_seeds():
     stat("mean energy (4 bands)", lambda r: _bands(r["mean_energy_e"], 4))
     stat("EEPF (8 bands)", lambda r: _bands(r["eepf"] * np.sqrt(np.arange(r["eepf"].size) + 0.5), 8))
     stat("counts", lambda r: np.array([r["ne"], r["ni"]]))
+
+
+def test_batched_sweep_equals_single_runs():
+    # Independent discharges advanced together on their own streams compute
+    # exactly what each computes alone.
+    import torch
+
+    from paper_2109_04469_amd import Discharge, step_many
+    from pic_inputs import sweep
+
+    sw = sweep.draw(6, seed=3, particles=(2_000, 20_000))
+    init = sweep.initial_states(sw, seed=5)
+    xs = xsec.argon_synthetic()
+    streams = [torch.cuda.Stream() for _ in sw]
+    batch = [Discharge(w["params"], xs, stream=s) for w, s in zip(sw, streams)]
+    for d, st in zip(batch, init):
+        for sp in (0, 1):
+            d.set_state(sp, *st[sp], step=0)
+    step_many(batch, 60, chunk=7)
+    torch.cuda.synchronize()
+    for w, st, d in zip(sw, init, batch):
+        assert d.sync() == 0
+        alone = Discharge(w["params"], xs)
+        for sp in (0, 1):
+            alone.set_state(sp, *st[sp], step=0)
+        alone.step(60)
+        assert alone.sync() == 0
+        for sp in (0, 1):
+            assert_state_equal(d.get_state(sp), alone.get_state(sp), what=f"{w['name']} sp {sp}")
+        assert np.array_equal(d.counters(), alone.counters())
