@@ -238,6 +238,45 @@ int pic_get_decisions(pic_handle* h, int species, uint8_t* codes, int64_t cap, i
  * enqueueing and are returned. Handles must be distinct. */
 int pic_step_many(pic_handle* const* handles, int n, int64_t n_steps, int64_t chunk);
 
+/* ---- batched launches --------------------------------------------------
+ * A batch advances n independent discharges (1 <= n <= 256, the same sweep
+ * as above) in lockstep with ONE launch per particle pass, field solve and
+ * tail for all of them: the kernels lay the discharges' particle tiles end
+ * to end, so that small discharges fill the GPU together instead of one at
+ * a time, and the launch count per step does not grow with n. The cell
+ * sorts stay per discharge.
+ *  - Handles: distinct, created on the same device with the same stream;
+ *    the batch enqueues everything on that stream. While a batch is in use
+ *    the handles may still be used one at a time (pic_step, pic_get_state,
+ *    ...); the batch only borrows them during pic_batch_step.
+ *  - Memory: the caller allocates a device workspace of
+ *    pic_batch_workspace_bytes() (256-byte aligned), where the per-step
+ *    kernel argument blocks go; the batch itself allocates two pinned host
+ *    staging buffers of half that size (released by pic_batch_free) and no
+ *    device memory.
+ *  - Results: every discharge computes exactly what pic_step on it alone
+ *    computes (bitwise). Device errors are latched per handle and returned
+ *    by pic_sync on that handle. Event timers (pic_timing) cover the sorts
+ *    only when stepping through a batch. */
+typedef struct pic_batch pic_batch;
+
+/* Workspace bytes of a batch of these handles. */
+int pic_batch_workspace_bytes(pic_handle* const* handles, int n, uint64_t* bytes);
+
+/* Creates a batch over the handles (borrowed, not owned: free the batch
+ * before the handles). PIC_EINVAL on a bad handle list or workspace. */
+int pic_batch_create(pic_handle* const* handles, int n, void* workspace, uint64_t workspace_bytes,
+                     pic_batch** out);
+
+/* Advances every discharge of the batch by n_steps. Asynchronous on the
+ * batch's stream, except that it waits for the GPU to have read the argument
+ * blocks of the previous chunk of steps (64 steps or fewer per chunk) before
+ * reusing their host buffer. */
+int pic_batch_step(pic_batch* b, int64_t n_steps);
+
+/* Synchronises the batch's stream and releases its host memory. */
+void pic_batch_free(pic_batch* b);
+
 /* Kernel timing with HIP events recorded on the handle's stream
  * (measurement surface). level 0: off. level 1: two event records around
  * the field kernel, each species' particle pass (PIC_TIMER_ELECTRON,

@@ -84,6 +84,11 @@ def load():
     L.pic_get_state.argtypes = [P, ctypes.c_int, P, P, P, P, i64, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     L.pic_step.argtypes = [P, i64]
     L.pic_step_many.argtypes = [ctypes.POINTER(P), ctypes.c_int, i64, i64]
+    L.pic_batch_workspace_bytes.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.POINTER(u64)]
+    L.pic_batch_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P, u64, ctypes.POINTER(P)]
+    L.pic_batch_step.argtypes = [P, i64]
+    L.pic_batch_free.argtypes = [P]
+    L.pic_batch_free.restype = None
     L.pic_sync.argtypes = [P]
     L.pic_set_field.argtypes = [P, P]
     L.pic_get_field.argtypes = [P, P, P, P, P, P]
@@ -102,7 +107,7 @@ def load():
     L.pic_selftest_sqrt.argtypes = [P, P, i64, P]
     L.pic_selftest_copy.argtypes = [P, P, i64, P]
     for name in ("pic_workspace_bytes", "pic_init", "pic_set_state", "pic_get_state", "pic_step",
-                 "pic_step_many",
+                 "pic_step_many", "pic_batch_workspace_bytes", "pic_batch_create", "pic_batch_step",
                  "pic_sync", "pic_set_field", "pic_get_field", "pic_measure", "pic_moments",
                  "pic_get_counters", "pic_get_decisions", "pic_get_derived",
                  "pic_selftest_philox", "pic_selftest_sqrt", "pic_selftest_copy", "pic_timing",

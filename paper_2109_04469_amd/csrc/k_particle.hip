@@ -212,62 +212,27 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
   o = alive ? mul : 0u;
 }
 
+// The tiles t_begin, t_begin + t_step, ... below t_end of one particle pass
+// of discharge a: push, wall and candidacy decisions, decision codes, tile
+// totals and the deposit of the new positions. sH (and, measuring, sEW) are
+// all zero on entry and on exit; sE holds a's field.
 template <int SP, bool MEASURE>
-__global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int nx = a.nx;
-  double* sE = reinterpret_cast<double*>(smem);
-  unsigned long long* sH = reinterpret_cast<unsigned long long*>(sE + nx);
-  double* sEW = reinterpret_cast<double*>(sH + nx);                 // MEASURE
-  unsigned int* sEEPF = reinterpret_cast<unsigned int*>(sEW + nx);  // MEASURE
-
-  __shared__ uint32_t s_tot[3][kDB / kWave];
-  __shared__ int s_lo, s_hi;
-  __shared__ unsigned long long s_cnt[NCOUNTERS];
-
+__device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int t_end, int t_step,
+                                             int64_t n_push, int64_t n_tot, const double* sE,
+                                             unsigned long long* sH, double* sEW,
+                                             unsigned int* sEEPF, uint32_t (*s_tot)[kDB / kWave],
+                                             int& s_lo, int& s_hi, unsigned long long* s_cnt) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
-  DevCtl* ctl = a.ctl;
-  const int par = a.parity;
-
-  for (int j = tid; j < nx; j += kDB) {
-    sE[j] = a.E[j];
-    sH[j] = 0ull;
-    if (MEASURE) sEW[j] = 0.0;
-  }
-  if (MEASURE)
-    for (int b = tid; b < a.nbins; b += kDB) sEEPF[b] = 0u;
-  if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
-  if (tid == 0) {
-    s_lo = INT_MAX;
-    s_hi = -1;
-  }
-
-  // slots [0, n_push) are pushed; [n_push, n_tot) were born earlier in this
-  // step (ions from this step's electron pass) and are carried unchanged
-  int64_t n_push = uniform64(SP == 0 ? ctl->n_e[par] : ctl->n_i[par]);
-  int64_t n_tot = SP == 0 ? n_push : n_push + uniform64(ctl->i_births);
-  if (n_tot > a.cap) {
-    if (tid == 0 && blockIdx.x == 0) latch_error(ctl, kErrCapacity);
-    n_tot = a.cap;
-    if (n_push > n_tot) n_push = n_tot;
-  }
-  const int ntiles = uniform32((int)((n_tot + kTile - 1) / kTile));
-
-  if (blockIdx.x == 0 && tid == 0) {
-    if (a.record) ctl->ncodes[SP] = n_push;
-    atomicAdd(&ctl->counters[SP == 0 ? C_E_PUSHED : C_I_PUSHED], (unsigned long long)n_push);
-  }
-  __syncthreads();
-
+  const int nx = a.nx;
   const uint32_t step = a.step;
   const double inv_dx = a.inv_dx;
   const double L = a.L;
   const bool no_coll = a.no_coll != 0;
   const uint64_t cand_thr = no_coll ? 0ull : a.pcoll_thr;
 
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (int t = t_begin; t < t_end; t += t_step) {
     const int64_t base = (int64_t)t * kTile;
     uint32_t own = 0, births = 0, rares = 0;
     int jlo = INT_MAX, jhi = -1;
@@ -432,6 +397,57 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
     }
     __syncthreads();
   }
+}
+
+template <int SP, bool MEASURE>
+__global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nx = a.nx;
+  double* sE = reinterpret_cast<double*>(smem);
+  unsigned long long* sH = reinterpret_cast<unsigned long long*>(sE + nx);
+  double* sEW = reinterpret_cast<double*>(sH + nx);                 // MEASURE
+  unsigned int* sEEPF = reinterpret_cast<unsigned int*>(sEW + nx);  // MEASURE
+
+  __shared__ uint32_t s_tot[3][kDB / kWave];
+  __shared__ int s_lo, s_hi;
+  __shared__ unsigned long long s_cnt[NCOUNTERS];
+
+  const int tid = threadIdx.x;
+  DevCtl* ctl = a.ctl;
+  const int par = a.parity;
+
+  for (int j = tid; j < nx; j += kDB) {
+    sE[j] = a.E[j];
+    sH[j] = 0ull;
+    if (MEASURE) sEW[j] = 0.0;
+  }
+  if (MEASURE)
+    for (int b = tid; b < a.nbins; b += kDB) sEEPF[b] = 0u;
+  if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
+  if (tid == 0) {
+    s_lo = INT_MAX;
+    s_hi = -1;
+  }
+
+  // slots [0, n_push) are pushed; [n_push, n_tot) were born earlier in this
+  // step (ions from this step's electron pass) and are carried unchanged
+  int64_t n_push = uniform64(SP == 0 ? ctl->n_e[par] : ctl->n_i[par]);
+  int64_t n_tot = SP == 0 ? n_push : n_push + uniform64(ctl->i_births);
+  if (n_tot > a.cap) {
+    if (tid == 0 && blockIdx.x == 0) latch_error(ctl, kErrCapacity);
+    n_tot = a.cap;
+    if (n_push > n_tot) n_push = n_tot;
+  }
+  const int ntiles = uniform32((int)((n_tot + kTile - 1) / kTile));
+
+  if (blockIdx.x == 0 && tid == 0) {
+    if (a.record) ctl->ncodes[SP] = n_push;
+    atomicAdd(&ctl->counters[SP == 0 ? C_E_PUSHED : C_I_PUSHED], (unsigned long long)n_push);
+  }
+  __syncthreads();
+
+  decide_tiles<SP, MEASURE>(a, blockIdx.x, ntiles, gridDim.x, n_push, n_tot, sE, sH, sEW, sEEPF,
+                            s_tot, s_lo, s_hi, s_cnt);
 
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
   if (MEASURE) {
@@ -481,51 +497,38 @@ __device__ __forceinline__ void reload(const PartArgs& a, const double* E, int64
 constexpr int kEPairs = kPPT / 2;
 static_assert(kPPT % 2 == 0, "k_emit takes pairs of slots");
 
+// Counts of a particle pass with no slots.
 template <int SP>
-__global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* sE = reinterpret_cast<double*>(smem);
-  __shared__ uint32_t s_wtot[kEPairs][kBlock / kWave];
-  __shared__ uint32_t s_woff[kEPairs][kBlock / kWave];
-  __shared__ uint64_t s_red[3][kBlock / kWave];
-  __shared__ uint32_t s_agg, s_qn;
+__device__ __forceinline__ void emit_empty(DevCtl* ctl, int par) {
+  ctl->n_rare[SP] = 0;
+  ctl->pbase[0] = ctl->pool_n[0];
+  ctl->pbase[1] = ctl->pool_n[1];
+  if (SP == 0) {
+    ctl->e_out = 0;
+    ctl->n_e[par ^ 1] = 0;
+    ctl->i_births = 0;
+    ctl->n_i[par ^ 1] = ctl->n_i[par];
+  } else {
+    ctl->n_i[par ^ 1] = 0;
+    ctl->n_e[par ^ 1] = ctl->e_out;
+  }
+}
 
+// The contiguous tiles [t0, t1) of a particle pass of discharge a (ntiles
+// tiles, n_tot slots): compacted outputs, queued rare slots and, at the last
+// tile, the pass's counts. sE holds a's field; s_qn is zero on entry.
+template <int SP>
+__device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, int ntiles,
+                                           int64_t n_tot, int64_t bbase, const double* sE,
+                                           uint32_t (*s_wtot)[kBlock / kWave],
+                                           uint32_t (*s_woff)[kBlock / kWave],
+                                           uint64_t (*s_red)[kBlock / kWave], uint32_t& s_agg,
+                                           uint32_t& s_qn) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
   DevCtl* ctl = a.ctl;
   const int par = a.parity;
-
-  int64_t n_push = uniform64(SP == 0 ? ctl->n_e[par] : ctl->n_i[par]);
-  int64_t n_tot = SP == 0 ? n_push : n_push + uniform64(ctl->i_births);
-  if (n_tot > a.cap) n_tot = a.cap;  // k_decide has latched the error
-  const int64_t bbase = uniform64(SP == 0 ? ctl->n_i[par] : ctl->e_out);
-  const int ntiles = uniform32((int)((n_tot + kTile - 1) / kTile));
-
-  if (ntiles == 0) {
-    if (blockIdx.x == 0 && tid == 0) {
-      ctl->n_rare[SP] = 0;
-      ctl->pbase[0] = ctl->pool_n[0];
-      ctl->pbase[1] = ctl->pool_n[1];
-      if (SP == 0) {
-        ctl->e_out = 0;
-        ctl->n_e[par ^ 1] = 0;
-        ctl->i_births = 0;
-        ctl->n_i[par ^ 1] = ctl->n_i[par];
-      } else {
-        ctl->n_i[par ^ 1] = 0;
-        ctl->n_e[par ^ 1] = ctl->e_out;
-      }
-    }
-    return;
-  }
-  // this workgroup's contiguous run of tiles
-  const int t0 = uniform32((int)((int64_t)ntiles * blockIdx.x / gridDim.x));
-  const int t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
-  if (t0 >= t1) return;
-
-  for (int j = tid; j < a.nx; j += kBlock) sE[j] = a.E[j];
-  if (tid == 0) s_qn = 0;
   // outputs, births and queued slots of all earlier tiles
   unsigned long long po = 0, pb = 0, pr = 0;
   for (int t = tid; t < t0; t += kBlock) {
@@ -674,6 +677,39 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
     __syncthreads();  // s_woff, s_agg and s_qn are reused by the next tile
     if (tid == 0) s_qn = 0;
   }
+}
+
+template <int SP>
+__global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sE = reinterpret_cast<double*>(smem);
+  __shared__ uint32_t s_wtot[kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_woff[kEPairs][kBlock / kWave];
+  __shared__ uint64_t s_red[3][kBlock / kWave];
+  __shared__ uint32_t s_agg, s_qn;
+
+  const int tid = threadIdx.x;
+  DevCtl* ctl = a.ctl;
+  const int par = a.parity;
+
+  int64_t n_push = uniform64(SP == 0 ? ctl->n_e[par] : ctl->n_i[par]);
+  int64_t n_tot = SP == 0 ? n_push : n_push + uniform64(ctl->i_births);
+  if (n_tot > a.cap) n_tot = a.cap;  // k_decide has latched the error
+  const int64_t bbase = uniform64(SP == 0 ? ctl->n_i[par] : ctl->e_out);
+  const int ntiles = uniform32((int)((n_tot + kTile - 1) / kTile));
+
+  if (ntiles == 0) {
+    if (blockIdx.x == 0 && tid == 0) emit_empty<SP>(ctl, par);
+    return;
+  }
+  // this workgroup's contiguous run of tiles
+  const int t0 = uniform32((int)((int64_t)ntiles * blockIdx.x / gridDim.x));
+  const int t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
+  if (t0 >= t1) return;
+
+  for (int j = tid; j < a.nx; j += kBlock) sE[j] = a.E[j];
+  if (tid == 0) s_qn = 0;
+  emit_tiles<SP>(a, t0, t1, ntiles, n_tot, bbase, sE, s_wtot, s_woff, s_red, s_agg, s_qn);
 }
 
 // ---------------------------------------------------------------------------
@@ -880,6 +916,226 @@ hipError_t launch_tail(int species, const FieldArgs& f, const PartArgs& a, int r
 }
 
 // ---------------------------------------------------------------------------
+// Batched passes: one launch runs the same pass of many independent
+// discharges. A kernel takes n argument blocks in device memory, one per
+// discharge, and lays the discharges' tiles (or queued slots) end to end;
+// each workgroup takes a contiguous run of that sequence and switches
+// discharge at the boundaries, so that small discharges share the chip
+// instead of each leaving most of it idle.
+
+// Exclusive prefix sums of v (one value per thread, threads at or beyond n
+// hold none) into out[0..n], out[n] being the total. NT threads, n <= NT.
+// Ends with a barrier.
+template <int NT>
+__device__ __forceinline__ void block_exclusive(int64_t v, int n, int64_t* out, int64_t* s_w) {
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  if (tid >= n) v = 0;
+  const int64_t inc = wave_incl_scan<int64_t>(v);
+  if (lane == kWave - 1) s_w[wave] = inc;
+  __syncthreads();
+  int64_t off = 0;
+  for (int w = 0; w < wave; ++w) off += s_w[w];
+  if (tid < n) out[tid] = off + inc - v;
+  if (tid == NT - 1) out[n] = off + inc;
+  __syncthreads();
+}
+
+// Slots of a particle pass of discharge a: [0, n_push) are pushed and
+// [n_push, n_tot) carried, clamped to the capacity.
+template <int SP>
+__device__ __forceinline__ void pass_slots(const PartArgs& a, int64_t& n_push, int64_t& n_tot) {
+  const DevCtl* ctl = a.ctl;
+  n_push = SP == 0 ? ctl->n_e[a.parity] : ctl->n_i[a.parity];
+  n_tot = SP == 0 ? n_push : n_push + ctl->i_births;
+  if (n_tot > a.cap) {
+    n_tot = a.cap;
+    if (n_push > n_tot) n_push = n_tot;
+  }
+}
+
+// First discharge at or after d whose run of the sequence ends beyond t.
+__device__ __forceinline__ int next_owner(const int64_t* s_start, int n, int d, int64_t t) {
+  while (d < n && s_start[d + 1] <= t) ++d;
+  return uniform32(d);
+}
+
+// This workgroup's run [tb, te) of a sequence of T items.
+__device__ __forceinline__ void wg_run(int64_t T, int64_t& tb, int64_t& te) {
+  tb = uniform64(T * (int64_t)blockIdx.x / (int64_t)gridDim.x);
+  te = uniform64(T * ((int64_t)blockIdx.x + 1) / (int64_t)gridDim.x);
+}
+
+template <int SP, bool MEASURE>
+__global__ __launch_bounds__(kDB) void k_decide_b(const PartArgs* __restrict__ args, int n,
+                                                  int nx_max, int nbins_max) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sE = reinterpret_cast<double*>(smem);
+  unsigned long long* sH = reinterpret_cast<unsigned long long*>(sE + nx_max);
+  double* sEW = reinterpret_cast<double*>(sH + nx_max);                 // MEASURE
+  unsigned int* sEEPF = reinterpret_cast<unsigned int*>(sEW + nx_max);  // MEASURE
+
+  __shared__ uint32_t s_tot[3][kDB / kWave];
+  __shared__ int s_lo, s_hi;
+  __shared__ unsigned long long s_cnt[NCOUNTERS];
+  __shared__ int64_t s_ts[kMaxBatch + 1];
+  __shared__ int64_t s_w[kDB / kWave];
+
+  const int tid = threadIdx.x;
+  for (int j = tid; j < nx_max; j += kDB) {
+    sH[j] = 0ull;
+    if (MEASURE) sEW[j] = 0.0;
+  }
+  if (MEASURE)
+    for (int b = tid; b < nbins_max; b += kDB) sEEPF[b] = 0u;
+  if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
+  if (tid == 0) {
+    s_lo = INT_MAX;
+    s_hi = -1;
+  }
+
+  int64_t tiles = 0;
+  if (tid < n) {
+    const PartArgs& a = args[tid];
+    int64_t n_push, n_tot;
+    pass_slots<SP>(a, n_push, n_tot);
+    tiles = (n_tot + kTile - 1) / kTile;
+    if (blockIdx.x == 0) {
+      DevCtl* ctl = a.ctl;
+      const int64_t np = SP == 0 ? ctl->n_e[a.parity] : ctl->n_i[a.parity];
+      if ((SP == 0 ? np : np + ctl->i_births) > a.cap) latch_error(ctl, kErrCapacity);
+      if (a.record) ctl->ncodes[SP] = n_push;
+      atomicAdd(&ctl->counters[SP == 0 ? C_E_PUSHED : C_I_PUSHED], (unsigned long long)n_push);
+    }
+  }
+  block_exclusive<kDB>(tiles, n, s_ts, s_w);
+  int64_t tb, te;
+  wg_run(uniform64(s_ts[n]), tb, te);
+  int d = next_owner(s_ts, n, 0, tb);
+  for (int64_t t = tb; t < te;) {
+    const PartArgs& a = args[d];
+    const int64_t ts = uniform64(s_ts[d]);
+    const int64_t se = min(te, uniform64(s_ts[d + 1]));
+    int64_t n_push, n_tot;
+    pass_slots<SP>(a, n_push, n_tot);
+    n_push = uniform64(n_push);
+    n_tot = uniform64(n_tot);
+    for (int j = tid; j < a.nx; j += kDB) sE[j] = a.E[j];
+    __syncthreads();
+    decide_tiles<SP, MEASURE>(a, (int)(t - ts), (int)(se - ts), 1, n_push, n_tot, sE, sH, sEW,
+                              sEEPF, s_tot, s_lo, s_hi, s_cnt);
+    // this discharge's event counts and EEPF counts
+    if (tid < NCOUNTERS) {
+      if (s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
+      s_cnt[tid] = 0ull;
+    }
+    if (MEASURE) {
+      for (int b = tid; b < a.nbins; b += kDB)
+        if (sEEPF[b]) {
+          atomicAdd(&a.eepf[b], (unsigned long long)sEEPF[b]);
+          sEEPF[b] = 0u;
+        }
+    }
+    __syncthreads();  // sE is refilled for the next discharge
+    t = se;
+    d = next_owner(s_ts, n, d + 1, t);
+  }
+}
+
+template <int SP>
+__global__ __launch_bounds__(kBlock) void k_emit_b(const PartArgs* __restrict__ args, int n) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sE = reinterpret_cast<double*>(smem);
+  __shared__ uint32_t s_wtot[kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_woff[kEPairs][kBlock / kWave];
+  __shared__ uint64_t s_red[3][kBlock / kWave];
+  __shared__ uint32_t s_agg, s_qn;
+  __shared__ int64_t s_ts[kMaxBatch + 1];
+  __shared__ int64_t s_w[kBlock / kWave];
+
+  const int tid = threadIdx.x;
+  int64_t tiles = 0;
+  if (tid < n) {
+    const PartArgs& a = args[tid];
+    int64_t n_push, n_tot;
+    pass_slots<SP>(a, n_push, n_tot);
+    tiles = (n_tot + kTile - 1) / kTile;
+    if (tiles == 0 && blockIdx.x == 0) emit_empty<SP>(a.ctl, a.parity);
+  }
+  block_exclusive<kBlock>(tiles, n, s_ts, s_w);
+  int64_t tb, te;
+  wg_run(uniform64(s_ts[n]), tb, te);
+  int d = next_owner(s_ts, n, 0, tb);
+  for (int64_t t = tb; t < te;) {
+    const PartArgs& a = args[d];
+    const int64_t ts = uniform64(s_ts[d]);
+    const int64_t tn = uniform64(s_ts[d + 1]);
+    const int64_t se = min(te, tn);
+    int64_t n_push, n_tot;
+    pass_slots<SP>(a, n_push, n_tot);
+    n_tot = uniform64(n_tot);
+    const DevCtl* ctl = a.ctl;
+    const int64_t bbase = uniform64(SP == 0 ? ctl->n_i[a.parity] : ctl->e_out);
+    for (int j = tid; j < a.nx; j += kBlock) sE[j] = a.E[j];
+    if (tid == 0) s_qn = 0;
+    emit_tiles<SP>(a, (int)(t - ts), (int)(se - ts), (int)(tn - ts), n_tot, bbase, sE, s_wtot,
+                   s_woff, s_red, s_agg, s_qn);
+    t = se;
+    d = next_owner(s_ts, n, d + 1, t);
+  }
+}
+
+// Queued slots of n discharges laid end to end (s_rs: prefix of their
+// counts), entries i0, i0 + stride, ...
+template <int SP>
+__device__ __forceinline__ void rare_run(const PartArgs* __restrict__ args, int n,
+                                         const int64_t* s_rs, int64_t i0, int64_t stride) {
+  const int64_t R = s_rs[n];
+  for (int64_t i = i0; i < R; i += stride) {
+    // the last discharge whose run starts at or before i
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_rs[mid] <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    const PartArgs& a = args[lo];
+    const uint4 q = a.rq[i - s_rs[lo]];
+    const int64_t bbase = SP == 0 ? a.ctl->n_i[a.parity] : a.ctl->e_out;
+    rare_slot<SP>(a, a.ctl->counters, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
+  }
+}
+
+template <int SP>
+__global__ __launch_bounds__(kBlock) void k_rare_b(const PartArgs* __restrict__ args, int n) {
+  __shared__ int64_t s_rs[kMaxBatch + 1];
+  __shared__ int64_t s_w[kBlock / kWave];
+  const int tid = threadIdx.x;
+  block_exclusive<kBlock>(tid < n ? args[tid].ctl->n_rare[SP] : 0, n, s_rs, s_w);
+  const int64_t nb = gridDim.x;
+  rare_run<SP>(args, n, s_rs, (int64_t)blockIdx.x + nb * tid, nb * kBlock);
+}
+
+// Workgroups [0, nf) solve the next step's field of nf discharges; the
+// others take the queued slots of the last particle pass of n discharges.
+template <int SP>
+__global__ __launch_bounds__(kFieldThreads) void k_tail_b(const FieldArgs* __restrict__ f, int nf,
+                                                          const PartArgs* __restrict__ args,
+                                                          int n) {
+  if ((int)blockIdx.x < nf) {
+    field_block(f[blockIdx.x]);
+    return;
+  }
+  __shared__ int64_t s_rs[kMaxBatch + 1];
+  __shared__ int64_t s_w[kFieldThreads / kWave];
+  const int tid = threadIdx.x;
+  block_exclusive<kFieldThreads>(tid < n ? args[tid].ctl->n_rare[SP] : 0, n, s_rs, s_w);
+  const int64_t nb = gridDim.x - nf;
+  rare_run<SP>(args, n, s_rs, (int64_t)(blockIdx.x - nf) + nb * tid, nb * kFieldThreads);
+}
+
+// ---------------------------------------------------------------------------
 // host side
 
 static size_t decide_lds(int nx, bool measure, int nbins) {
@@ -948,6 +1204,74 @@ hipError_t launch_particle_kernel(int kernel, int species, bool measure, const P
     else
       hipLaunchKernelGGL((k_rare<1>), dim3(c.grid_rare), dim3(kBlock), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+BatchLaunch batch_launch_config(int nx_max, int nbins_max, int num_cu, const int64_t max_tiles[2]) {
+  BatchLaunch c{};
+  c.nx_max = nx_max;
+  c.nbins_max = nbins_max;
+  for (int sp = 0; sp < 2; ++sp) {
+    for (int m = 0; m < 2; ++m) {
+      c.lds_decide[sp][m] = decide_lds(nx_max, m == 1, nbins_max);
+      int bpc;
+      if (sp == 0)
+        bpc = m ? blocks_per_cu(k_decide_b<0, true>, c.lds_decide[sp][m], kDB)
+                : blocks_per_cu(k_decide_b<0, false>, c.lds_decide[sp][m], kDB);
+      else
+        bpc = blocks_per_cu(k_decide_b<1, false>, c.lds_decide[sp][m], kDB);
+      c.grid_decide[sp][m] = clamp_grid((int64_t)bpc * num_cu, max_tiles[sp]);
+    }
+  }
+  c.lds_emit = emit_lds(nx_max);
+  for (int sp = 0; sp < 2; ++sp) {
+    const int bpc = sp == 0 ? blocks_per_cu(k_emit_b<0>, c.lds_emit)
+                            : blocks_per_cu(k_emit_b<1>, c.lds_emit);
+    c.grid_emit[sp] = clamp_grid((int64_t)bpc * num_cu, max_tiles[sp]);
+  }
+  c.grid_rare = num_cu * 2;
+  return c;
+}
+
+hipError_t launch_batch_pass(int kernel, int species, bool measure, const PartArgs* args, int n,
+                             const BatchLaunch& c, hipStream_t s) {
+  if (n < 1 || n > kMaxBatch || species < 0 || species > 1) return hipErrorInvalidValue;
+  const int m = (species == 0 && measure) ? 1 : 0;
+  if (kernel == 0) {
+    const dim3 g(c.grid_decide[species][m]);
+    const size_t lds = c.lds_decide[species][m];
+    if (species == 1)
+      hipLaunchKernelGGL((k_decide_b<1, false>), g, dim3(kDB), lds, s, args, n, c.nx_max,
+                         c.nbins_max);
+    else if (m)
+      hipLaunchKernelGGL((k_decide_b<0, true>), g, dim3(kDB), lds, s, args, n, c.nx_max,
+                         c.nbins_max);
+    else
+      hipLaunchKernelGGL((k_decide_b<0, false>), g, dim3(kDB), lds, s, args, n, c.nx_max,
+                         c.nbins_max);
+  } else if (kernel == 1) {
+    if (species == 0)
+      hipLaunchKernelGGL((k_emit_b<0>), dim3(c.grid_emit[0]), dim3(kBlock), c.lds_emit, s, args, n);
+    else
+      hipLaunchKernelGGL((k_emit_b<1>), dim3(c.grid_emit[1]), dim3(kBlock), c.lds_emit, s, args, n);
+  } else {
+    if (species == 0)
+      hipLaunchKernelGGL((k_rare_b<0>), dim3(c.grid_rare), dim3(kBlock), 0, s, args, n);
+    else
+      hipLaunchKernelGGL((k_rare_b<1>), dim3(c.grid_rare), dim3(kBlock), 0, s, args, n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_tail(int species, const FieldArgs* f, int nf, const PartArgs* args, int n,
+                             int rare_blocks, hipStream_t s) {
+  if (nf < 0 || nf > kMaxBatch || n < 0 || n > kMaxBatch || rare_blocks < 1)
+    return hipErrorInvalidValue;
+  const dim3 g(nf + rare_blocks);
+  if (species == 0)
+    hipLaunchKernelGGL((k_tail_b<0>), g, dim3(kFieldThreads), 0, s, f, nf, args, n);
+  else
+    hipLaunchKernelGGL((k_tail_b<1>), g, dim3(kFieldThreads), 0, s, f, nf, args, n);
   return hipGetLastError();
 }
 

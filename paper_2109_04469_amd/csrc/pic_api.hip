@@ -11,6 +11,18 @@
 
 using namespace pic;
 
+struct pic_batch {
+  std::vector<pic_handle*> hs;
+  hipStream_t stream;
+  BatchLaunch launch;
+  int chunk;          // steps per upload of argument blocks
+  size_t step_bytes;  // argument bytes of one step (worst case)
+  unsigned char* dev[2];
+  unsigned char* host[2];
+  hipEvent_t copied[2];
+  int slot;
+};
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -299,6 +311,194 @@ int repack_species(pic_handle* h, int sp) {
   return PIC_OK;
 }
 
+FieldArgs field_args(pic_handle* h, int field_mode_, bool ion_step) {
+  const int par = (int)(h->step & 1);
+  FieldArgs f{};
+  f.dep_e = h->dep_e[par];
+  f.dep_i = h->dep_i[h->cur_hi];
+  f.zero_a = h->dep_e[par ^ 1];
+  f.zero_b = ion_step ? h->dep_i[1 - h->cur_hi] : nullptr;
+  f.rho = h->rho;
+  f.phi = h->phi;
+  f.E = h->Ebuf[par];
+  f.th_cp = h->th_cp;
+  f.th_m = h->th_m;
+  f.acc_ne = h->acc_ne;
+  f.acc_ni = h->acc_ni;
+  f.acc_w = h->acc_w;
+  f.ctl = h->ctl;
+  f.V = h->vtab[(size_t)(h->step % h->p.steps_per_cycle)];
+  f.dx = h->dx;
+  f.qfac32 = h->qfac32;
+  f.nfac32 = h->nfac32;
+  f.kpois = h->kpois;
+  f.nx = h->nx;
+  f.mode = field_mode_;
+  f.measuring = h->measuring;
+  f.parity = par;
+  return f;
+}
+
+bool is_ion_step(const pic_handle* h, int64_t step) {
+  return !(h->p.flags & PIC_FLAG_IMMOBILE_IONS) && (step % h->p.ion_subcycle == 0);
+}
+
+constexpr int kTailRareBlocks = 128;
+
+// What one step of one discharge launches, in order:
+//   [field(n)]  e_decide e_emit  [e_rare i_decide i_emit on ion steps]
+//   then either the tail (queued slots of the last pass + field(n+1)) when
+//   another step follows, or the last pass's rare kernel alone;
+//   then a sort or repack of each species when due.
+struct StepPlan {
+  bool field_first;  // solve this step's field before the passes
+  FieldArgs ff;
+  bool measure;
+  PartArgs ae;
+  bool ion;
+  PartArgs ai;
+  int pend_sp;  // species of the last pass, whose queued slots run last
+  bool tail;    // the next step's field is solved with those slots
+  FieldArgs fn;
+  int post;     // 0: nothing, 1: sort, 2: repack (both species)
+  SortArgs sa[2];
+};
+
+// Plans the next step of h and advances the host-side schedule state past
+// it (buffer parities, step index). field_ready: this step's field was
+// solved by the previous step's tail; last: no step follows in this call.
+StepPlan plan_step(pic_handle* h, bool field_ready, bool last) {
+  StepPlan q{};
+  const pic_params& p = h->p;
+  const int mode = field_mode(h);
+  const int par = (int)(h->step & 1);
+  q.ion = is_ion_step(h, h->step);
+  q.field_first = !field_ready;
+  if (q.field_first) q.ff = field_args(h, mode, q.ion);
+  h->e_last = par;
+  q.measure = h->measuring != 0;
+  q.ae = particle_args(h, 0, par);
+  h->cur[0] ^= 1;
+  q.pend_sp = 0;
+  if (q.ion) {
+    // the ions take this step's ionization ions with their velocities
+    q.ai = particle_args(h, 1, par);
+    h->cur[1] ^= 1;
+    h->cur_hi ^= 1;
+    q.pend_sp = 1;
+  }
+  h->step += 1;
+  q.tail = !last;
+  if (q.tail) q.fn = field_args(h, mode, is_ion_step(h, h->step));
+  q.post = 0;
+  if (p.sort_interval > 0 && h->step % p.sort_interval == 0) {
+    // stable sort by cell; the pool is rebuilt in the new slot order
+    q.post = 1;
+    for (int sp = 0; sp < 2; ++sp) {
+      q.sa[sp] = sort_args(h, sp, true);
+      h->cur[sp] ^= 1;
+      h->pcur[sp] ^= 1;
+    }
+  } else if ((p.sort_interval == 0 || p.sort_interval > kRepackSteps) &&
+             h->step % kRepackSteps == 0) {
+    // pool rebuilt in slot order: drops the entries of absorbed particles
+    q.post = 2;
+    for (int sp = 0; sp < 2; ++sp) {
+      q.sa[sp] = sort_args(h, sp, false);
+      h->pcur[sp] ^= 1;
+    }
+  }
+  return q;
+}
+
+int launch_post(pic_handle* h, const StepPlan& q, hipStream_t s) {
+  for (int sp = 0; sp < 2; ++sp) {
+    if (q.post == 1) {
+      const int ev = timer_begin(h);
+      HIP_TRY(launch_sort(q.sa[sp], s));
+      timer_end(h, PIC_TIMER_SORT, ev);
+    } else if (q.post == 2) {
+      HIP_TRY(launch_repack(q.sa[sp], s));
+    }
+  }
+  return PIC_OK;
+}
+
+// One planned step on the handle's own stream, with the opt-in timers.
+int launch_step(pic_handle* h, const StepPlan& q) {
+  hipStream_t s = h->stream;
+  if (q.field_first) {
+    const int ev = timer_begin(h);
+    HIP_TRY(launch_field(q.ff, s));
+    timer_end(h, PIC_TIMER_FIELD, ev);
+  }
+  const int e_pass = timer_begin(h);
+  for (int k = 0; k < 2; ++k) {
+    const int ev = h->timing >= 2 ? timer_begin(h) : -1;
+    HIP_TRY(launch_particle_kernel(k, 0, q.measure, q.ae, h->launch[0], s));
+    timer_end(h, k == 0 ? PIC_TIMER_E_DECIDE : PIC_TIMER_E_EMIT, ev);
+  }
+  int pend_pass = e_pass;
+  if (q.ion) {
+    const int ev = h->timing >= 2 ? timer_begin(h) : -1;
+    HIP_TRY(launch_particle_kernel(2, 0, q.measure, q.ae, h->launch[0], s));
+    timer_end(h, PIC_TIMER_E_RARE, ev);
+    timer_end(h, PIC_TIMER_ELECTRON, e_pass);
+    const int i_pass = timer_begin(h);
+    for (int k = 0; k < 2; ++k) {
+      const int ev2 = h->timing >= 2 ? timer_begin(h) : -1;
+      HIP_TRY(launch_particle_kernel(k, 1, false, q.ai, h->launch[1], s));
+      timer_end(h, k == 0 ? PIC_TIMER_I_DECIDE : PIC_TIMER_I_EMIT, ev2);
+    }
+    pend_pass = i_pass;
+  }
+  const PartArgs& pend = q.pend_sp == 0 ? q.ae : q.ai;
+  const int ev = h->timing >= 2 ? timer_begin(h) : -1;
+  if (q.tail)
+    HIP_TRY(launch_tail(q.pend_sp, q.fn, pend, kTailRareBlocks, s));
+  else
+    HIP_TRY(launch_particle_kernel(2, q.pend_sp, q.measure, pend, h->launch[q.pend_sp], s));
+  timer_end(h, q.pend_sp == 0 ? PIC_TIMER_E_RARE : PIC_TIMER_I_RARE, ev);
+  timer_end(h, q.pend_sp == 0 ? PIC_TIMER_ELECTRON : PIC_TIMER_ION, pend_pass);
+  return launch_post(h, q, s);
+}
+
+// Batched stepping: per step, the argument blocks of every discharge's
+// passes go to device memory (one upload per chunk of steps, double
+// buffered through pinned host memory) and each pass is one launch for all.
+constexpr size_t kBatchUploadBytes = (size_t)4 << 20;  // per chunk buffer
+constexpr size_t kBatchArrayAlign = 64;
+
+size_t batch_step_bytes(int n) {
+  // field blocks: this step's (first step of a call) and the next step's;
+  // particle blocks: electron passes, electron passes of ion steps (their
+  // queued slots run before the ions), ion passes, and the electron passes
+  // whose queued slots run in the tail
+  const size_t f = (size_t)n * sizeof(FieldArgs);
+  const size_t a = (size_t)n * sizeof(PartArgs);
+  auto al = [](size_t v) { return (v + kBatchArrayAlign - 1) / kBatchArrayAlign * kBatchArrayAlign; };
+  return 2 * al(f) + 4 * al(a);
+}
+
+int batch_chunk_steps(int n) {
+  const size_t per = batch_step_bytes(n);
+  size_t c = kBatchUploadBytes / per;
+  if (c < 1) c = 1;
+  if (c > 64) c = 64;
+  return (int)c;
+}
+
+int check_batch_handles(pic_handle* const* hs, int n) {
+  if (!hs || n < 1 || n > kMaxBatch) return PIC_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i]) return PIC_EINVAL;
+    if (hs[i]->stream != hs[0]->stream || hs[i]->device != hs[0]->device) return PIC_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (hs[k] == hs[i]) return PIC_EINVAL;
+  }
+  return PIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -566,124 +766,19 @@ int pic_get_state(pic_handle* h, int species, double* x, double* vx, double* vy,
   return PIC_OK;
 }
 
-FieldArgs field_args(pic_handle* h, int field_mode_, bool ion_step) {
-  const int par = (int)(h->step & 1);
-  FieldArgs f{};
-  f.dep_e = h->dep_e[par];
-  f.dep_i = h->dep_i[h->cur_hi];
-  f.zero_a = h->dep_e[par ^ 1];
-  f.zero_b = ion_step ? h->dep_i[1 - h->cur_hi] : nullptr;
-  f.rho = h->rho;
-  f.phi = h->phi;
-  f.E = h->Ebuf[par];
-  f.th_cp = h->th_cp;
-  f.th_m = h->th_m;
-  f.acc_ne = h->acc_ne;
-  f.acc_ni = h->acc_ni;
-  f.acc_w = h->acc_w;
-  f.ctl = h->ctl;
-  f.V = h->vtab[(size_t)(h->step % h->p.steps_per_cycle)];
-  f.dx = h->dx;
-  f.qfac32 = h->qfac32;
-  f.nfac32 = h->nfac32;
-  f.kpois = h->kpois;
-  f.nx = h->nx;
-  f.mode = field_mode_;
-  f.measuring = h->measuring;
-  f.parity = par;
-  return f;
-}
-
-bool is_ion_step(const pic_handle* h, int64_t step) {
-  return !(h->p.flags & PIC_FLAG_IMMOBILE_IONS) && (step % h->p.ion_subcycle == 0);
-}
-
-constexpr int kTailRareBlocks = 128;
-
-// One step. Launch order on the handle's stream:
-//   [field(n)]  e_decide e_emit  (e_rare i_decide i_emit on ion steps)
-//   then either tail(rare of the last pass + field(n+1)) when another step
-//   follows in this call, or the last pass's rare kernel alone.
-// A sort or repack of the particle arrays, when due, comes after that.
 int pic_step(pic_handle* h, int64_t n_steps) {
   if (!h || n_steps < 0) return PIC_EINVAL;
   if ((h->p.flags & PIC_FLAG_FIXED_E) && !h->field_fixed_set) return PIC_ESTATE;
-  const pic_params& p = h->p;
-  const int mode = field_mode(h);
-  bool field_ready = false;  // field of h->step already enqueued by a tail
+  bool field_ready = false;
   for (int64_t it = 0; it < n_steps; ++it) {
-    const int par = (int)(h->step & 1);
-    const bool ion_step = is_ion_step(h, h->step);
-    if (!field_ready) {
-      const int ev = timer_begin(h);
-      HIP_TRY(launch_field(field_args(h, mode, ion_step), h->stream));
-      timer_end(h, PIC_TIMER_FIELD, ev);
-    }
-    h->e_last = par;
-    const bool measure = h->measuring != 0;
-
-    // electron pass
-    const PartArgs ae = particle_args(h, 0, par);
-    const int e_pass = timer_begin(h);
-    for (int k = 0; k < 2; ++k) {
-      const int ev = h->timing >= 2 ? timer_begin(h) : -1;
-      HIP_TRY(launch_particle_kernel(k, 0, measure, ae, h->launch[0], h->stream));
-      timer_end(h, k == 0 ? PIC_TIMER_E_DECIDE : PIC_TIMER_E_EMIT, ev);
-    }
-    h->cur[0] ^= 1;
-    int pend_sp = 0, pend_pass = e_pass;
-    PartArgs pend = ae;
-    if (ion_step) {
-      // the ions take this step's ionization ions with their velocities
-      const int ev = h->timing >= 2 ? timer_begin(h) : -1;
-      HIP_TRY(launch_particle_kernel(2, 0, measure, ae, h->launch[0], h->stream));
-      timer_end(h, PIC_TIMER_E_RARE, ev);
-      timer_end(h, PIC_TIMER_ELECTRON, e_pass);
-      const PartArgs ai = particle_args(h, 1, par);
-      const int i_pass = timer_begin(h);
-      for (int k = 0; k < 2; ++k) {
-        const int ev2 = h->timing >= 2 ? timer_begin(h) : -1;
-        HIP_TRY(launch_particle_kernel(k, 1, false, ai, h->launch[1], h->stream));
-        timer_end(h, k == 0 ? PIC_TIMER_I_DECIDE : PIC_TIMER_I_EMIT, ev2);
-      }
-      h->cur[1] ^= 1;
-      h->cur_hi ^= 1;
-      pend_sp = 1;
-      pend_pass = i_pass;
-      pend = ai;
-    }
-    h->step += 1;
-
-    // the last pass's queued slots, with the next step's field if one follows
-    const int rare_timer = pend_sp == 0 ? PIC_TIMER_E_RARE : PIC_TIMER_I_RARE;
-    const int ev = h->timing >= 2 ? timer_begin(h) : -1;
-    if (it + 1 < n_steps) {
-      HIP_TRY(launch_tail(pend_sp, field_args(h, mode, is_ion_step(h, h->step)), pend,
-                          kTailRareBlocks, h->stream));
-      field_ready = true;
-    } else {
-      HIP_TRY(launch_particle_kernel(2, pend_sp, measure, pend, h->launch[pend_sp], h->stream));
-      field_ready = false;
-    }
-    timer_end(h, rare_timer, ev);
-    timer_end(h, pend_sp == 0 ? PIC_TIMER_ELECTRON : PIC_TIMER_ION, pend_pass);
-
-    if (p.sort_interval > 0 && h->step % p.sort_interval == 0) {
-      int s = sort_species(h, 0);
-      if (s) return s;
-      s = sort_species(h, 1);
-      if (s) return s;
-    } else if ((p.sort_interval == 0 || p.sort_interval > kRepackSteps) &&
-               h->step % kRepackSteps == 0) {
-      int s = repack_species(h, 0);
-      if (s) return s;
-      s = repack_species(h, 1);
-      if (s) return s;
-    }
+    const StepPlan q = plan_step(h, field_ready, it + 1 == n_steps);
+    const int st = launch_step(h, q);
+    if (st) return st;
+    field_ready = q.tail;
     // keep the event backlog bounded
     if (h->ev_used.size() >= 4096) {
-      const int st = timer_collect(h);
-      if (st) return st;
+      const int c = timer_collect(h);
+      if (c) return c;
     }
   }
   return PIC_OK;
@@ -704,6 +799,190 @@ int pic_step_many(pic_handle* const* handles, int n, int64_t n_steps, int64_t ch
     }
   }
   return PIC_OK;
+}
+
+int pic_batch_workspace_bytes(pic_handle* const* handles, int n, uint64_t* bytes) {
+  if (!bytes) return PIC_EINVAL;
+  const int v = check_batch_handles(handles, n);
+  if (v) return v;
+  *bytes = 2 * (uint64_t)batch_chunk_steps(n) * batch_step_bytes(n);
+  return PIC_OK;
+}
+
+int pic_batch_create(pic_handle* const* handles, int n, void* workspace, uint64_t workspace_bytes,
+                     pic_batch** out) {
+  if (!out) return PIC_EINVAL;
+  *out = nullptr;
+  const int v = check_batch_handles(handles, n);
+  if (v) return v;
+  const int chunk = batch_chunk_steps(n);
+  const size_t per = batch_step_bytes(n);
+  const size_t half = (size_t)chunk * per;
+  if (!workspace || workspace_bytes < 2 * half || ((uintptr_t)workspace % kAlign) != 0)
+    return PIC_EINVAL;
+  pic_batch* b = new (std::nothrow) pic_batch();
+  if (!b) return PIC_EINVAL;
+  b->hs.assign(handles, handles + n);
+  b->stream = handles[0]->stream;
+  b->chunk = chunk;
+  b->step_bytes = per;
+  b->slot = 0;
+  int nx_max = 0, nbins_max = 0;
+  int64_t tiles[2] = {0, 0};
+  for (pic_handle* h : b->hs) {
+    nx_max = h->nx > nx_max ? h->nx : nx_max;
+    nbins_max = h->p.eepf_bins > nbins_max ? h->p.eepf_bins : nbins_max;
+    tiles[0] += h->max_tiles[0];
+    tiles[1] += h->max_tiles[1];
+  }
+  b->launch = batch_launch_config(nx_max, nbins_max, handles[0]->num_cu, tiles);
+  for (int k = 0; k < 2; ++k) {
+    b->dev[k] = static_cast<unsigned char*>(workspace) + k * half;
+    b->host[k] = nullptr;
+    b->copied[k] = nullptr;
+  }
+  bool ok = true;
+  for (int k = 0; k < 2 && ok; ++k) {
+    ok = hipHostMalloc((void**)&b->host[k], half, hipHostMallocDefault) == hipSuccess &&
+         hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming) == hipSuccess;
+  }
+  if (!ok) {
+    pic_batch_free(b);
+    return PIC_EHIP;
+  }
+  *out = b;
+  return PIC_OK;
+}
+
+int pic_batch_step(pic_batch* b, int64_t n_steps) {
+  if (!b || n_steps < 0) return PIC_EINVAL;
+  for (pic_handle* h : b->hs)
+    if ((h->p.flags & PIC_FLAG_FIXED_E) && !h->field_fixed_set) return PIC_ESTATE;
+  const int n = (int)b->hs.size();
+  hipStream_t s = b->stream;
+  const BatchLaunch& c = b->launch;
+
+  // one step's launches: device addresses of its argument arrays and counts
+  struct StepLaunch {
+    const FieldArgs* ff;
+    const FieldArgs* fn;
+    const PartArgs* ed;  // measuring discharges first
+    const PartArgs* er;
+    const PartArgs* ia;
+    const PartArgs* t0;
+    int nff, nem, nion, nt0;
+    bool tail;
+  };
+  struct Post {
+    int step;
+    int discharge;
+    StepPlan q;
+  };
+  std::vector<StepPlan> plans(n);
+  std::vector<StepLaunch> steps;
+  std::vector<Post> posts;
+  bool field_ready = false;
+  for (int64_t done = 0; done < n_steps;) {
+    const int m = (int)((n_steps - done < b->chunk) ? n_steps - done : b->chunk);
+    const int slot = b->slot;
+    b->slot ^= 1;
+    // the last upload from this host buffer has been read
+    HIP_TRY(hipEventSynchronize(b->copied[slot]));
+    unsigned char* H = b->host[slot];
+    unsigned char* D = b->dev[slot];
+    size_t off = 0;
+    steps.clear();
+    posts.clear();
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off += (bytes + kBatchArrayAlign - 1) / kBatchArrayAlign * kBatchArrayAlign;
+      return o;
+    };
+    for (int k = 0; k < m; ++k) {
+      const bool last = done + k + 1 == n_steps;
+      for (int i = 0; i < n; ++i) plans[i] = plan_step(b->hs[i], field_ready, last);
+      field_ready = !last;
+      StepLaunch L{};
+      L.tail = !last;
+      const size_t o_ff = take(n * sizeof(FieldArgs)), o_fn = take(n * sizeof(FieldArgs));
+      const size_t o_ed = take(n * sizeof(PartArgs)), o_er = take(n * sizeof(PartArgs));
+      const size_t o_ia = take(n * sizeof(PartArgs)), o_t0 = take(n * sizeof(PartArgs));
+      FieldArgs* ff = reinterpret_cast<FieldArgs*>(H + o_ff);
+      FieldArgs* fn = reinterpret_cast<FieldArgs*>(H + o_fn);
+      PartArgs* ed = reinterpret_cast<PartArgs*>(H + o_ed);
+      PartArgs* er = reinterpret_cast<PartArgs*>(H + o_er);
+      PartArgs* ia = reinterpret_cast<PartArgs*>(H + o_ia);
+      PartArgs* t0 = reinterpret_cast<PartArgs*>(H + o_t0);
+      int ne = 0;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < n; ++i)
+          if (plans[i].measure == (pass == 0)) {
+            ed[ne++] = plans[i].ae;
+            if (pass == 0) L.nem += 1;
+          }
+      for (int i = 0; i < n; ++i) {
+        const StepPlan& q = plans[i];
+        if (q.field_first) ff[L.nff++] = q.ff;
+        if (L.tail) fn[i] = q.fn;
+        if (q.ion) {
+          er[L.nion] = q.ae;
+          ia[L.nion++] = q.ai;
+        } else {
+          t0[L.nt0++] = q.ae;
+        }
+        if (q.post) posts.push_back(Post{k, i, q});
+      }
+      L.ff = reinterpret_cast<const FieldArgs*>(D + o_ff);
+      L.fn = reinterpret_cast<const FieldArgs*>(D + o_fn);
+      L.ed = reinterpret_cast<const PartArgs*>(D + o_ed);
+      L.er = reinterpret_cast<const PartArgs*>(D + o_er);
+      L.ia = reinterpret_cast<const PartArgs*>(D + o_ia);
+      L.t0 = reinterpret_cast<const PartArgs*>(D + o_t0);
+      steps.push_back(L);
+    }
+    HIP_TRY(hipMemcpyAsync(D, H, off, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(b->copied[slot], s));
+    size_t pi = 0;
+    for (int k = 0; k < m; ++k) {
+      const StepLaunch& L = steps[k];
+      if (L.nff) HIP_TRY(launch_batch_field(L.ff, L.nff, s));
+      if (L.nem) HIP_TRY(launch_batch_pass(0, 0, true, L.ed, L.nem, c, s));
+      if (n > L.nem) HIP_TRY(launch_batch_pass(0, 0, false, L.ed + L.nem, n - L.nem, c, s));
+      HIP_TRY(launch_batch_pass(1, 0, false, L.ed, n, c, s));
+      if (L.nion) {
+        HIP_TRY(launch_batch_pass(2, 0, false, L.er, L.nion, c, s));
+        HIP_TRY(launch_batch_pass(0, 1, false, L.ia, L.nion, c, s));
+        HIP_TRY(launch_batch_pass(1, 1, false, L.ia, L.nion, c, s));
+      }
+      if (L.tail) {
+        if (L.nion) {
+          HIP_TRY(launch_batch_tail(1, L.fn, n, L.ia, L.nion, kTailRareBlocks, s));
+          if (L.nt0) HIP_TRY(launch_batch_pass(2, 0, false, L.t0, L.nt0, c, s));
+        } else {
+          HIP_TRY(launch_batch_tail(0, L.fn, n, L.t0, L.nt0, kTailRareBlocks, s));
+        }
+      } else {
+        if (L.nt0) HIP_TRY(launch_batch_pass(2, 0, false, L.t0, L.nt0, c, s));
+        if (L.nion) HIP_TRY(launch_batch_pass(2, 1, false, L.ia, L.nion, c, s));
+      }
+      for (; pi < posts.size() && posts[pi].step == k; ++pi) {
+        const int st = launch_post(b->hs[posts[pi].discharge], posts[pi].q, s);
+        if (st) return st;
+      }
+    }
+    done += m;
+  }
+  return PIC_OK;
+}
+
+void pic_batch_free(pic_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  for (int k = 0; k < 2; ++k) {
+    if (b->host[k]) (void)hipHostFree(b->host[k]);
+    if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
+  }
+  delete b;
 }
 
 int pic_sync(pic_handle* h) {

@@ -149,6 +149,26 @@ hipError_t launch_particle_kernel(int kernel, int species, bool measure, const P
 // this step's last particle pass of `species` (rare_blocks workgroups)
 hipError_t launch_tail(int species, const FieldArgs& f, const PartArgs& a, int rare_blocks,
                        hipStream_t s);
+// Batched launches over n discharges (n <= kMaxBatch): args and f are
+// arrays of argument blocks in device memory, one per discharge.
+constexpr int kMaxBatch = 256;
+struct BatchLaunch {
+  int grid_decide[2][2];  // [species][measuring]
+  size_t lds_decide[2][2];
+  int grid_emit[2];
+  size_t lds_emit;
+  int grid_rare;
+  int nx_max;
+  int nbins_max;
+};
+// max_tiles: the largest number of tiles a pass of each species can have,
+// summed over the discharges
+BatchLaunch batch_launch_config(int nx_max, int nbins_max, int num_cu, const int64_t max_tiles[2]);
+hipError_t launch_batch_pass(int kernel, int species, bool measure, const PartArgs* args, int n,
+                             const BatchLaunch& c, hipStream_t s);
+hipError_t launch_batch_tail(int species, const FieldArgs* f, int nf, const PartArgs* args, int n,
+                             int rare_blocks, hipStream_t s);
+hipError_t launch_batch_field(const FieldArgs* f, int n, hipStream_t s);
 hipError_t launch_sort(const SortArgs& a, hipStream_t s);
 // pool repacked in slot order (no reordering of the slots)
 hipError_t launch_repack(const SortArgs& a, hipStream_t s);

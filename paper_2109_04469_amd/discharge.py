@@ -229,3 +229,41 @@ def step_many(discharges, n_steps, chunk=50):
     L = capi.load()
     arr = (ctypes.c_void_p * len(discharges))(*[d.h.value for d in discharges])
     check(L.pic_step_many(arr, len(discharges), int(n_steps), int(chunk)), "pic_step_many")
+
+
+class Batch:
+    """Independent discharges advanced in lockstep with one launch per
+    particle pass, field solve and tail for all of them (libpic
+    pic_batch_*). The discharges must share one stream; they stay usable on
+    their own between batch steps and must outlive the batch."""
+
+    def __init__(self, discharges):
+        self.L = capi.load()
+        self.discharges = list(discharges)
+        n = len(self.discharges)
+        self._arr = (ctypes.c_void_p * n)(*[d.h.value for d in self.discharges])
+        nbytes = ctypes.c_uint64()
+        check(self.L.pic_batch_workspace_bytes(self._arr, n, ctypes.byref(nbytes)),
+              "pic_batch_workspace_bytes")
+        dev = self.discharges[0].device
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        h = ctypes.c_void_p()
+        check(self.L.pic_batch_create(self._arr, n, ctypes.c_void_p(base + off), nbytes.value,
+                                      ctypes.byref(h)), "pic_batch_create")
+        self.h = h
+
+    def step(self, n=1):
+        check(self.L.pic_batch_step(self.h, int(n)), "pic_batch_step")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pic_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -426,3 +426,60 @@ def test_batched_sweep_equals_single_runs():
         for sp in (0, 1):
             assert_state_equal(d.get_state(sp), alone.get_state(sp), what=f"{w['name']} sp {sp}")
         assert np.array_equal(d.counters(), alone.counters())
+
+
+def test_batched_launches_equal_single_runs():
+    # One launch per pass for all discharges of a batch: each discharge
+    # computes exactly what it computes alone, across calls and upload
+    # chunks, with mixed ion sub-cycling, sort intervals and measurement.
+    import torch
+
+    from paper_2109_04469_amd import Batch, Discharge
+    from pic_inputs import sweep
+
+    sw = sweep.draw(6, seed=11, particles=(2_000, 20_000))
+    sw[1]["params"]["ion_subcycle"] = 3
+    sw[4]["params"]["ion_subcycle"] = 4
+    sw[2]["params"]["sort_interval"] = 20
+    sw[3]["params"]["sort_interval"] = 0
+    init = sweep.initial_states(sw, seed=7)
+    xs = xsec.argon_synthetic()
+    stream = torch.cuda.Stream()
+    ds = [Discharge(w["params"], xs, stream=stream) for w in sw]
+    for d, st in zip(ds, init):
+        for sp in (0, 1):
+            d.set_state(sp, *st[sp], step=0)
+    for k in (0, 5):
+        ds[k].measure(True)
+    b = Batch(ds)
+    b.step(100)   # two upload chunks
+    b.step(1)
+    b.step(29)
+    torch.cuda.synchronize()
+    for k, (w, st, d) in enumerate(zip(sw, init, ds)):
+        assert d.sync() == 0
+        alone = Discharge(w["params"], xs)
+        for sp in (0, 1):
+            alone.set_state(sp, *st[sp], step=0)
+        if k in (0, 5):
+            alone.measure(True)
+        alone.step(130)
+        assert alone.sync() == 0
+        assert alone.step_index == d.step_index == 130
+        for sp in (0, 1):
+            assert_state_equal(d.get_state(sp), alone.get_state(sp), what=f"{w['name']} sp {sp}")
+        assert np.array_equal(d.counters(), alone.counters())
+        f1, f2 = d.get_field(), alone.get_field()
+        for key in ("E", "dep_e", "dep_i"):
+            assert np.array_equal(f1[key], f2[key]), key
+        if k in (0, 5):
+            m1, m2 = d.moments(), alone.moments()
+            # densities and EEPF come from integer counts; the energy weights
+            # are FP64 atomic sums whose order is not fixed
+            for key in ("n_e", "n_i", "eepf"):
+                assert np.array_equal(m1[key], m2[key]), key
+            np.testing.assert_allclose(m1["mean_energy_e"], m2["mean_energy_e"], rtol=1e-12)
+    # a single discharge may still step alone after batch steps
+    ds[2].step(3)
+    assert ds[2].sync() == 0
+    b.close()
