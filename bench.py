@@ -25,6 +25,10 @@ library's plain streaming copy on 2 x 256 MiB, the achievable-bandwidth
 reference on the same GPU.
 cpu_baseline: the CPU oracle (single thread) on a bounded sample of the same
 workload.
+sweep: the batched-sweep workload (64 seeded independent discharges of
+uneven size), advanced one discharge after the other, on one stream each,
+and as one batch with one launch per pass for all; throughputs, speedups
+over the one-after-the-other run, and whether all three agree bitwise.
 """
 import argparse
 import json
@@ -42,7 +46,7 @@ BYTES_PER_PARTICLE_STEP = 64
 # rocprofv3 FETCH_SIZE (x2, the factor a plain copy of known size gives)
 # and WRITE_SIZE (x1) at c3; to be re-measured whenever the pass's kernels
 # change (None when not measured for the current kernels)
-PASS_TRAFFIC_BYTES_PER_PARTICLE = 59.65
+PASS_TRAFFIC_BYTES_PER_PARTICLE = 59.86
 
 DESCRIPTIONS = {
     "c3_large_lowp": ("gap 6.7 cm, 2048 cells, dt=T_RF/8000, 13.56 MHz, 500 V, 2 Pa, gamma 0.2, R 0.5, "
@@ -99,6 +103,92 @@ def copy_reference(torch, nbytes=1 << 28, reps=20):
             "us_per_copy": ms * 1e3, "kernel": "k_selftest_copy"}
 
 
+def sweep_measurement(torch, steps, n=64, log=print):
+    """The batched-sweep workload: n seeded independent discharges (N_t in
+    [500, 8000], 64-1024 cells, 20k-2M particles per species, R, gamma,
+    pressure and voltage drawn), each advanced by `steps` steps from its
+    initial state three ways on the same GPU: one after the other with
+    pic_step (the plain single-run method), all at once on their own streams
+    (pic_step_many), and as one batch with one launch per pass for all
+    (pic_batch_step). The three compute the same particle-steps bitwise."""
+    from paper_2109_04469_amd import Batch, Discharge, step_many
+    from pic_inputs import sweep, xsec
+
+    sw = sweep.draw(n, seed=0, capacity_factor=4)
+    init = sweep.initial_states(sw, seed=0)
+    xs = xsec.argon_synthetic()
+
+    def reset(ds):
+        for d, st in zip(ds, init):
+            for sp in (0, 1):
+                d.set_state(sp, *st[sp], step=0)
+        torch.cuda.synchronize()
+
+    def timed(ds, fn):
+        reset(ds)
+        c0 = [d.counters() for d in ds]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for d in ds:
+            st = d.sync()
+            assert st == 0, f"sweep discharge failed: status {st}"
+        c1 = [d.counters() for d in ds]
+        ps = sum(int((b[1] - a[1]) + (b[2] - a[2])) for a, b in zip(c0, c1))
+        return {"value": ps / (t1 - t0), "seconds": t1 - t0}, ps, [b - a for a, b in zip(c0, c1)]
+
+    def snapshot(ds):
+        return [tuple(t.clone() for t in d.get_state(sp, to_numpy=False)) for d in ds for sp in (0, 1)]
+
+    def same(a, b):
+        return all(all(torch.equal(x, y) for x, y in zip(p, q)) for p, q in zip(a, b))
+
+    one = torch.cuda.Stream()
+    ds = [Discharge(w["params"], xs, stream=one) for w in sw]
+
+    def sequential():
+        for d in ds:
+            d.step(steps)
+
+    log(f"[bench] sweep: {n} discharges x {steps} steps, sequential")
+    seq, ps, cnt_seq = timed(ds, sequential)
+    ref = snapshot(ds)
+    batch = Batch(ds)
+    log("[bench] sweep: batched launches")
+    bat, ps_b, cnt_b = timed(ds, lambda: batch.step(steps))
+    equal = ps_b == ps and same(ref, snapshot(ds)) and all(
+        (a == b).all() for a, b in zip(cnt_seq, cnt_b))
+    batch.close()
+    del batch, ds
+    torch.cuda.empty_cache()
+
+    log("[bench] sweep: one stream per discharge")
+    streams = [torch.cuda.Stream() for _ in sw]
+    ds = [Discharge(w["params"], xs, stream=s_) for w, s_ in zip(sw, streams)]
+    mst, ps_m, cnt_m = timed(ds, lambda: step_many(ds, steps, chunk=50))
+    equal = equal and ps_m == ps and same(ref, snapshot(ds))
+    del ds
+    torch.cuda.empty_cache()
+    sizes = [w["n_init"][0] for w in sw]
+    return {
+        "workload": (f"{n} seeded discharges (sweep seed 0): N_t in [500, 8000], 64-1024 cells, "
+                     f"{min(sizes)}-{max(sizes)} particles per species ({sum(sizes)} in all), "
+                     "R in [0, 0.7], gamma in [0, 0.4], 2-100 Pa, 100-500 V, ion_subcycle 1, "
+                     "sort every 50 steps; each advanced from its initial state"),
+        "steps": steps,
+        "particle_steps": ps,
+        "unit": "particle-steps/s",
+        "sequential": seq,
+        "streams": mst,
+        "batched": bat,
+        "speedup_batched_vs_sequential": bat["value"] / seq["value"],
+        "speedup_streams_vs_sequential": mst["value"] / seq["value"],
+        "bitwise_equal": bool(equal),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +198,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=50, help="oracle steps for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--sweep-steps", type=int, default=200, help="steps of the batched-sweep workload")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the batched-sweep workload")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="run only the batched-sweep workload and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs one discharge on one GPU; --gpus {args.gpus} is not supported "
@@ -116,6 +210,12 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.sweep_only:
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        print(json.dumps({"sweep": sweep_measurement(
+            torch, args.sweep_steps, log=lambda *a: print(*a, file=sys.stderr, flush=True))}))
+        return
 
     from paper_2109_04469_amd import Discharge
     from pic_inputs import state, workloads, xsec
@@ -228,6 +328,11 @@ def main():
         "cpu_baseline": None,
         "copy_ref": copy_reference(torch),
     }
+    out["sweep"] = None
+    if not args.no_sweep:
+        del d
+        torch.cuda.empty_cache()
+        out["sweep"] = sweep_measurement(torch, args.sweep_steps, log=log)
     if not args.no_cpu:
         log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(w, init, xs, args.cpu_steps)
