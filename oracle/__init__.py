@@ -15,7 +15,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = [os.path.join(HERE, "pic_oracle.c"), os.path.join(HERE, "philox.c")]
+SOURCES = [os.path.join(HERE, "pic_oracle.c"), os.path.join(HERE, "philox.c"),
+           os.path.join(HERE, "warm_oracle.c")]
 CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
 NCOUNTERS = 16
@@ -76,6 +77,10 @@ def lib():
         L.ora_thomas.argtypes = [ctypes.c_int64, d, d, d, d, d]
         L.ora_poisson.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, d, d]
         L.ora_efield.argtypes = [ctypes.c_int32, ctypes.c_double, d, d, d]
+        L.ora_load_profile.argtypes = [d, d, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                       ctypes.c_int64, d, d, d, d]
+        L.ora_load_profile.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -165,6 +170,19 @@ def efield(nx, dx, rho, phi):
     E = np.zeros(nx)
     lib().ora_efield(nx, dx, _dp(rho), _dp(phi), _dp(E))
     return E
+
+
+def load_profile(dens, temp_ev, L, vfac, seed, run, species, n):
+    """Particles drawn from a density and a temperature profile on [0, L]
+    (warm_oracle.c): returns x, vx, vy, vz."""
+    dens = np.ascontiguousarray(dens, dtype=np.float64)
+    temp = np.ascontiguousarray(temp_ev, dtype=np.float64)
+    assert dens.shape == temp.shape and dens.size >= 2
+    out = [np.zeros(int(n)) for _ in range(4)]
+    st = lib().ora_load_profile(_dp(dens), _dp(temp), int(dens.size), float(L), float(vfac), int(seed),
+                                int(run), int(species), int(n), *[_dp(a) for a in out])
+    assert st == 0
+    return tuple(out)
 
 
 class Oracle:
