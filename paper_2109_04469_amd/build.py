@@ -15,8 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["k_field.hip", "k_particle.hip", "k_sort.hip", "k_misc.hip", "pic_api.hip"]
-HEADERS = ["pic_dev.h", "pic_internal.h"]
+SOURCES = ["k_field.hip", "k_particle.hip", "k_sort.hip", "k_misc.hip", "k_mlp.hip", "pic_api.hip",
+           "mlp_api.hip"]
+HEADERS = ["pic_dev.h", "pic_internal.h", "field_block.h", "mlp_internal.h"]
 ARCH = os.environ.get("PIC_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

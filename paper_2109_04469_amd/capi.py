@@ -89,6 +89,21 @@ def load():
     L.pic_batch_step.argtypes = [P, i64]
     L.pic_batch_free.argtypes = [P]
     L.pic_batch_free.restype = None
+    L.pic_load_profile.argtypes = [P, ctypes.c_int, i64, P, P, ctypes.c_int, i64]
+    f32 = ctypes.c_float
+    L.pic_mlp_workspace_bytes.argtypes = [ctypes.c_int] * 5 + [ctypes.POINTER(u64)]
+    L.pic_mlp_init.argtypes = [ctypes.c_int] * 5 + [P, u64, P, ctypes.POINTER(P)]
+    L.pic_mlp_num_params.argtypes = [P, ctypes.POINTER(i64)]
+    L.pic_mlp_set_params.argtypes = [P, P]
+    L.pic_mlp_get_params.argtypes = [P, P]
+    L.pic_mlp_forward.argtypes = [P, P, ctypes.c_int, P]
+    L.pic_mlp_grad.argtypes = [P, P, P, ctypes.c_int]
+    L.pic_mlp_get_grad.argtypes = [P, P]
+    L.pic_mlp_get_loss.argtypes = [P, ctypes.POINTER(f32)]
+    L.pic_mlp_adam.argtypes = [P, f32, f32, f32, f32, f32]
+    L.pic_mlp_train_step.argtypes = [P, P, P, ctypes.c_int, f32, f32, f32, f32, f32]
+    L.pic_mlp_free.argtypes = [P]
+    L.pic_mlp_free.restype = None
     L.pic_sync.argtypes = [P]
     L.pic_set_field.argtypes = [P, P]
     L.pic_get_field.argtypes = [P, P, P, P, P, P]
@@ -108,6 +123,9 @@ def load():
     L.pic_selftest_copy.argtypes = [P, P, i64, P]
     for name in ("pic_workspace_bytes", "pic_init", "pic_set_state", "pic_get_state", "pic_step",
                  "pic_step_many", "pic_batch_workspace_bytes", "pic_batch_create", "pic_batch_step",
+                 "pic_load_profile", "pic_mlp_workspace_bytes", "pic_mlp_init", "pic_mlp_num_params",
+                 "pic_mlp_set_params", "pic_mlp_get_params", "pic_mlp_forward", "pic_mlp_grad",
+                 "pic_mlp_get_grad", "pic_mlp_get_loss", "pic_mlp_adam", "pic_mlp_train_step",
                  "pic_sync", "pic_set_field", "pic_get_field", "pic_measure", "pic_moments",
                  "pic_get_counters", "pic_get_decisions", "pic_get_derived",
                  "pic_selftest_philox", "pic_selftest_sqrt", "pic_selftest_copy", "pic_timing",

@@ -24,6 +24,68 @@ hipError_t launch_deposit(const double* x, const int64_t* count, double inv_dx, 
   return hipGetLastError();
 }
 
+// Particles loaded from a density and a temperature profile given at npts
+// equally spaced points on [0, L], both linear in between. Slot i takes the
+// position whose cumulative density is u * (total) for its position uniform
+// u (inverse of the piecewise-quadratic cumulative function, solved in
+// closed form within the interval), and normal velocity components of
+// variance e T(x) / m. Every workgroup builds the cumulative masses of the
+// intervals in LDS in one fixed order.
+__global__ __launch_bounds__(256) void k_load_profile(LoadArgs a) {
+  extern __shared__ double sC[];  // sC[k]: mass of the intervals below point k
+  const int np = a.npts;
+  if (threadIdx.x == 0) {
+    double c = 0.0;
+    sC[0] = 0.0;
+    for (int k = 0; k + 1 < np; ++k) {
+      c = c + (fmax(a.dens[k], 0.0) + fmax(a.dens[k + 1], 0.0)) * a.hh;
+      sC[k + 1] = c;
+    }
+  }
+  __syncthreads();
+  const double total = sC[np - 1];
+  const double h = a.h;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint4 r0 = philox(make_uint4(kLoadStep, (uint32_t)i, 16u * a.species, 0u), a.seed, a.run);
+    const double r = u01(r0.x) * total;
+    // the last interval whose cumulative mass starts at or below r
+    int lo = 0, hi = np - 2;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sC[mid] <= r) lo = mid;
+      else hi = mid - 1;
+    }
+    const double rp = r - sC[lo];
+    const double da = fmax(a.dens[lo], 0.0), db = fmax(a.dens[lo + 1], 0.0);
+    const double den = da + sqrt(fmax(da * da + 2.0 * (db - da) * rp / h, 0.0));
+    double t = den > 0.0 ? 2.0 * rp / den : 0.0;
+    t = fmin(fmax(t, 0.0), h);
+    const double x = fmin((double)lo * h + t, a.L);
+    const double ta = a.temp[lo], tb = a.temp[lo + 1];
+    const double T = fmax(ta + (tb - ta) * (t / h), 0.0);
+    const double sig = sqrt(T * a.vfac);
+    const uint4 r1 = philox(make_uint4(kLoadStep, (uint32_t)i, 16u * a.species + 1u, 0u), a.seed,
+                            a.run);
+    double n1, n2, n3, n4;
+    box_muller(u01(r1.x), u01(r1.y), n1, n2);
+    box_muller(u01(r1.z), u01(r1.w), n3, n4);
+    a.x[i] = x;
+    a.vx[i] = sig * n1;
+    a.vy[i] = sig * n2;
+    a.vz[i] = sig * n3;
+  }
+}
+
+hipError_t launch_load_profile(const LoadArgs& a, hipStream_t s) {
+  if (a.npts < 2 || a.npts > kMaxLoadPoints) return hipErrorInvalidValue;
+  int64_t g = (a.n + 255) / 256;
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_load_profile, dim3((unsigned)g), dim3(256), (size_t)a.npts * 8, s, a);
+  return hipGetLastError();
+}
+
 __global__ void k_selftest_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                                   int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -7,6 +7,7 @@
 #include <new>
 #include <vector>
 
+#include "../../include/warmstart.h"
 #include "pic_internal.h"
 
 using namespace pic;
@@ -499,6 +500,49 @@ int check_batch_handles(pic_handle* const* hs, int n) {
   return PIC_OK;
 }
 
+// Replaces the particles of one species: fill(dst, pool) writes n positions
+// and x-velocities to the active slot buffers and n (v_y, v_z) to the active
+// pool (entry i for slot i); then the counts, pool indices and the species'
+// deposit are rebuilt and the event counters and error word cleared.
+// Synchronises.
+template <typename Fill>
+int replace_state(pic_handle* h, int species, int64_t n, int64_t step, Fill fill) {
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const int old_par = (int)(h->step & 1), par = (int)(step & 1);
+  if (old_par != par) {
+    // keep the other species' count and (for electrons) deposit on the new parity
+    if (species == 1) {
+      HIP_TRY(hipMemcpyAsync(&h->ctl->n_e[par], &h->ctl->n_e[old_par], 8,
+                             hipMemcpyDeviceToDevice, h->stream));
+      HIP_TRY(hipMemcpyAsync(h->dep_e[par], h->dep_e[old_par], (size_t)h->nx * 8,
+                             hipMemcpyDeviceToDevice, h->stream));
+    } else {
+      HIP_TRY(hipMemcpyAsync(&h->ctl->n_i[par], &h->ctl->n_i[old_par], 8,
+                             hipMemcpyDeviceToDevice, h->stream));
+    }
+  }
+  h->step = step;
+  double* const* dst = h->part[species][h->cur[species]];
+  double* const* pool = h->pool[species][h->pcur[species]];
+  if (n > 0) {
+    const int st = fill(dst, pool);
+    if (st) return st;
+  }
+  int64_t nn = n;
+  int64_t* cnt = species == 0 ? &h->ctl->n_e[par] : &h->ctl->n_i[par];
+  HIP_TRY(hipMemcpyAsync(cnt, &nn, 8, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(&h->ctl->pool_n[species], &nn, 8, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(launch_iota(h->pid[species][h->cur[species]], cnt, h->stream));
+  int64_t* dep = species == 0 ? h->dep_e[par] : h->dep_i[h->cur_hi];
+  HIP_TRY(hipMemsetAsync(dep, 0, (size_t)h->nx * 8, h->stream));
+  HIP_TRY(launch_deposit(dst[0], cnt, h->inv_dx, h->nx, reinterpret_cast<unsigned long long*>(dep),
+                         h->stream));
+  HIP_TRY(hipMemsetAsync(h->ctl->counters, 0, sizeof(h->ctl->counters), h->stream));
+  HIP_TRY(hipMemsetAsync(&h->ctl->err, 0, sizeof(uint32_t), h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return PIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -697,42 +741,40 @@ int pic_set_state(pic_handle* h, int species, const double* x, const double* vx,
   if (!h || species < 0 || species > 1 || n < 0 || step < 0) return PIC_EINVAL;
   if (n > 0 && (!x || !vx || !vy || !vz)) return PIC_EINVAL;
   if (n > h->p.capacity[species]) return PIC_ECAPACITY;
-  HIP_TRY(hipStreamSynchronize(h->stream));
-  const int old_par = (int)(h->step & 1), par = (int)(step & 1);
-  if (old_par != par) {
-    // keep the other species' count and (for electrons) deposit on the new parity
-    if (species == 1) {
-      HIP_TRY(hipMemcpyAsync(&h->ctl->n_e[par], &h->ctl->n_e[old_par], 8,
-                             hipMemcpyDeviceToDevice, h->stream));
-      HIP_TRY(hipMemcpyAsync(h->dep_e[par], h->dep_e[old_par], (size_t)h->nx * 8,
-                             hipMemcpyDeviceToDevice, h->stream));
-    } else {
-      HIP_TRY(hipMemcpyAsync(&h->ctl->n_i[par], &h->ctl->n_i[old_par], 8,
-                             hipMemcpyDeviceToDevice, h->stream));
-    }
-  }
-  h->step = step;
-  double* const* dst = h->part[species][h->cur[species]];
-  double* const* pool = h->pool[species][h->pcur[species]];
-  if (n > 0) {
+  return replace_state(h, species, n, step, [&](double* const* dst, double* const* pool) {
     HIP_TRY(hipMemcpyAsync(dst[0], x, (size_t)n * 8, hipMemcpyDefault, h->stream));
     HIP_TRY(hipMemcpyAsync(dst[1], vx, (size_t)n * 8, hipMemcpyDefault, h->stream));
     HIP_TRY(hipMemcpyAsync(pool[0], vy, (size_t)n * 8, hipMemcpyDefault, h->stream));
     HIP_TRY(hipMemcpyAsync(pool[1], vz, (size_t)n * 8, hipMemcpyDefault, h->stream));
-  }
-  int64_t nn = n;
-  int64_t* cnt = species == 0 ? &h->ctl->n_e[par] : &h->ctl->n_i[par];
-  HIP_TRY(hipMemcpyAsync(cnt, &nn, 8, hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(hipMemcpyAsync(&h->ctl->pool_n[species], &nn, 8, hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(launch_iota(h->pid[species][h->cur[species]], cnt, h->stream));
-  int64_t* dep = species == 0 ? h->dep_e[par] : h->dep_i[h->cur_hi];
-  HIP_TRY(hipMemsetAsync(dep, 0, (size_t)h->nx * 8, h->stream));
-  HIP_TRY(launch_deposit(dst[0], cnt, h->inv_dx, h->nx, reinterpret_cast<unsigned long long*>(dep),
-                         h->stream));
-  HIP_TRY(hipMemsetAsync(h->ctl->counters, 0, sizeof(h->ctl->counters), h->stream));
-  HIP_TRY(hipMemsetAsync(&h->ctl->err, 0, sizeof(uint32_t), h->stream));
-  HIP_TRY(hipStreamSynchronize(h->stream));
-  return PIC_OK;
+    return PIC_OK;
+  });
+}
+
+int pic_load_profile(pic_handle* h, int species, int64_t n, const double* dens, const double* temp_ev,
+                     int npts, int64_t step) {
+  if (!h || species < 0 || species > 1 || n < 0 || step < 0) return PIC_EINVAL;
+  if (npts < 2 || npts > kMaxLoadPoints || (n > 0 && (!dens || !temp_ev))) return PIC_EINVAL;
+  if (n > h->p.capacity[species]) return PIC_ECAPACITY;
+  return replace_state(h, species, n, step, [&](double* const* dst, double* const* pool) {
+    LoadArgs a{};
+    a.dens = dens;
+    a.temp = temp_ev;
+    a.x = dst[0];
+    a.vx = dst[1];
+    a.vy = pool[0];
+    a.vz = pool[1];
+    a.n = n;
+    a.L = h->L;
+    a.h = h->L / (double)(npts - 1);
+    a.hh = 0.5 * a.h;
+    a.vfac = kQe / h->mass[species];
+    a.npts = npts;
+    a.species = species;
+    a.seed = h->p.seed;
+    a.run = h->p.run;
+    HIP_TRY(launch_load_profile(a, h->stream));
+    return PIC_OK;
+  });
 }
 
 int pic_get_state(pic_handle* h, int species, double* x, double* vx, double* vy, double* vz,

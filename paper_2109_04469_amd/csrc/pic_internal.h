@@ -179,6 +179,27 @@ hipError_t launch_gather(const uint32_t* id, const double* vy, const double* vz,
                          double* out_z, int64_t n, hipStream_t s);
 hipError_t launch_deposit(const double* x, const int64_t* count, double inv_dx, int nx,
                           unsigned long long* dep, hipStream_t s);
+// particles drawn from density and temperature profiles (pic_load_profile)
+constexpr uint32_t kLoadStep = 0xFFFFFFFEu;  // counter word 0 of the loader's draws
+constexpr int kMaxLoadPoints = 8192;
+struct LoadArgs {
+  const double* dens;  // npts points on [0, L], device
+  const double* temp;  // temperature in eV at the same points, device
+  double* x;
+  double* vx;
+  double* vy;
+  double* vz;
+  int64_t n;
+  double L;
+  double h;    // L / (npts - 1)
+  double hh;   // h / 2
+  double vfac; // e / m
+  int npts;
+  int species;
+  uint32_t seed;
+  uint32_t run;
+};
+hipError_t launch_load_profile(const LoadArgs& a, hipStream_t s);
 hipError_t launch_selftest_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                                   int64_t n, hipStream_t s);
 hipError_t launch_selftest_sqrt(const double* in, double* out, int64_t n, hipStream_t s);

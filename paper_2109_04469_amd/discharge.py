@@ -120,6 +120,17 @@ class Discharge:
             return tuple(t.cpu().numpy() for t in out)
         return tuple(out)
 
+    def load_profile(self, species, n, dens, temp_ev, step=0):
+        """Replaces the species by n particles drawn from density and
+        temperature (eV) profiles at equally spaced points on [0, L]
+        (libpic pic_load_profile)."""
+        d = torch.as_tensor(np.asarray(dens, dtype=np.float64)).to(self.device)
+        t = torch.as_tensor(np.asarray(temp_ev, dtype=np.float64)).to(self.device)
+        assert d.numel() == t.numel()
+        torch.cuda.current_stream(self.device).synchronize()
+        check(self.L.pic_load_profile(self.h, int(species), int(n), _ptr(d), _ptr(t), d.numel(),
+                                      int(step)), "pic_load_profile")
+
     @property
     def step_index(self):
         n = ctypes.c_int64()
@@ -260,6 +271,88 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             self.L.pic_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mlp:
+    """The warm-start network on the GPU (libpic pic_mlp_*): n_in -> depth x
+    width (GELU) -> n_out, BF16 weights with FP32 master copy, FP32
+    accumulation, MSE loss, AdamW. Arrays are float32 torch tensors on the
+    device, row-major [batch, features]."""
+
+    def __init__(self, n_in, width, depth, n_out, max_batch, device="cuda:0", stream=None):
+        self.L = capi.load()
+        self.device = torch.device(device)
+        self.dims = (int(n_in), int(width), int(depth), int(n_out))
+        self.max_batch = int(max_batch)
+        nbytes = ctypes.c_uint64()
+        check(self.L.pic_mlp_workspace_bytes(*self.dims, self.max_batch, ctypes.byref(nbytes)),
+              "pic_mlp_workspace_bytes")
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        check(self.L.pic_mlp_init(*self.dims, self.max_batch, ctypes.c_void_p(base + off), nbytes.value,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+              "pic_mlp_init")
+        self.h = h
+        n = ctypes.c_int64()
+        check(self.L.pic_mlp_num_params(self.h, ctypes.byref(n)), "pic_mlp_num_params")
+        self.num_params = int(n.value)
+
+    def _f32(self, a):
+        t = torch.as_tensor(a).to(device=self.device, dtype=torch.float32).contiguous()
+        torch.cuda.current_stream(self.device).synchronize()
+        return t
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.num_params
+        check(self.L.pic_mlp_set_params(self.h, _ptr(p)), "pic_mlp_set_params")
+
+    def get_params(self):
+        p = np.zeros(self.num_params, np.float32)
+        check(self.L.pic_mlp_get_params(self.h, _ptr(p)), "pic_mlp_get_params")
+        return p
+
+    def forward(self, x):
+        x = self._f32(x)
+        y = torch.empty((x.shape[0], self.dims[3]), dtype=torch.float32, device=self.device)
+        check(self.L.pic_mlp_forward(self.h, _ptr(x), x.shape[0], _ptr(y)), "pic_mlp_forward")
+        self.stream.synchronize()
+        return y
+
+    def grad(self, x, target):
+        x, t = self._f32(x), self._f32(target)
+        check(self.L.pic_mlp_grad(self.h, _ptr(x), _ptr(t), x.shape[0]), "pic_mlp_grad")
+        g = np.zeros(self.num_params, np.float32)
+        check(self.L.pic_mlp_get_grad(self.h, _ptr(g)), "pic_mlp_get_grad")
+        return self.loss(), g
+
+    def loss(self):
+        v = ctypes.c_float()
+        check(self.L.pic_mlp_get_loss(self.h, ctypes.byref(v)), "pic_mlp_get_loss")
+        return float(v.value)
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        check(self.L.pic_mlp_adam(self.h, lr, beta1, beta2, eps, weight_decay), "pic_mlp_adam")
+
+    def train_step(self, x, target, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        """x, target: device float32 tensors (not copied; keep them alive until
+        the stream has run the step)."""
+        check(self.L.pic_mlp_train_step(self.h, _ptr(x), _ptr(target), x.shape[0], lr, beta1, beta2,
+                                        eps, weight_decay), "pic_mlp_train_step")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.pic_mlp_free(self.h)
             self.h = None
 
     def __del__(self):

@@ -9,9 +9,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "pic.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\s*\*)\s*(pic_\w+)\s*\(", src, re.M)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names.update(re.findall(r"^\s*(?:int|void|const char\s*\*)\s*(pic_\w+)\s*\(", src, re.M))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -23,7 +28,8 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) >= 17
+    assert len(names) >= 35
+    assert "pic_batch_step" in names and "pic_mlp_train_step" in names and "pic_load_profile" in names
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 

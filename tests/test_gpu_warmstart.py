@@ -1,0 +1,153 @@
+"""Warm-start kernels on the GPU (libpic through the C ABI) against the CPU
+oracles: the network's forward pass, gradient and AdamW step (BF16
+matrix-core products with FP32 accumulation) and the particle loader.
+
+Network tolerances. Both sides round the same operands to BFloat16, so the
+products agree up to the FP32 accumulation of at most a few hundred terms
+(relative 1e-6) and the rare operand whose rounding to BF16 goes the other
+way because its FP32 value differs in the last bits (one BF16 step, 2^-8,
+on one term of a sum). Tensors are therefore compared as
+max |gpu - oracle| <= tol * max |oracle| with tol = 2e-3 for outputs and
+5e-3 for gradients, and most elements agree far more closely (the median
+relative difference is checked at 1e-4).
+"""
+import numpy as np
+import pytest
+
+from gpu_common import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+QE = 1.602176634e-19
+ME = 9.1093837015e-31
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _net(n_in, width, depth, n_out, batch, seed):
+    from oracle import mlp
+
+    from paper_2109_04469_amd import Mlp
+
+    rng = np.random.default_rng(seed)
+    dims = mlp.dims_of(n_in, width, depth, n_out)
+    p = np.zeros(mlp.num_params(dims))
+    for (W, b) in mlp.unpack(p, dims):
+        W[...] = rng.normal(scale=np.sqrt(2.0 / W.shape[1]), size=W.shape)
+        b[...] = rng.normal(scale=0.1, size=b.shape)
+    p = p.astype(np.float32)
+    net = Mlp(n_in, width, depth, n_out, batch)
+    net.set_params(p)
+    x = rng.normal(size=(batch, n_in)).astype(np.float32)
+    t = rng.normal(size=(batch, n_out)).astype(np.float32)
+    return net, dims, p, x, t
+
+
+def _close(g, o, tol, what):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    scale = np.abs(o).max()
+    err = np.abs(g - o)
+    assert err.max() <= tol * scale, f"{what}: max err {err.max():.3g} vs scale {scale:.3g}"
+    rel = err / np.maximum(np.abs(o), 1e-3 * scale)
+    assert np.median(rel) <= 1e-4, f"{what}: median rel {np.median(rel):.3g}"
+
+
+@pytest.mark.parametrize("shape", [(6, 256, 4, 512, 64), (6, 40, 2, 45, 37), (3, 64, 0, 7, 5)])
+def test_forward_matches_oracle(shape):
+    from oracle import mlp
+
+    n_in, width, depth, n_out, batch = shape
+    net, dims, p, x, _ = _net(n_in, width, depth, n_out, batch, seed=sum(shape))
+    y = net.forward(x).cpu().numpy()
+    yo, _ = mlp.forward(p, x, dims)
+    _close(y, yo, 2e-3, f"forward {shape}")
+
+
+@pytest.mark.parametrize("shape", [(6, 256, 4, 512, 64), (6, 40, 2, 45, 37)])
+def test_gradient_matches_oracle(shape):
+    from oracle import mlp
+
+    n_in, width, depth, n_out, batch = shape
+    net, dims, p, x, t = _net(n_in, width, depth, n_out, batch, seed=7 + sum(shape))
+    loss, g = net.grad(x, t)
+    lo, go = mlp.loss_and_grad(p, x, t, dims)
+    assert loss == pytest.approx(lo, rel=2e-3)
+    for li, ((gW, gb), (oW, ob)) in enumerate(zip(mlp.unpack(g, dims), mlp.unpack(go, dims))):
+        _close(gW, oW, 5e-3, f"dW layer {li}")
+        _close(gb, ob, 5e-3, f"db layer {li}")
+
+
+def test_adamw_steps_match_oracle():
+    from oracle import mlp
+
+    net, dims, p, x, t = _net(6, 64, 2, 16, 32, seed=11)
+    w = p.astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    for step in range(1, 4):
+        cur = net.get_params()
+        _, g = net.grad(x, t)
+        net.adam(1e-3, 0.9, 0.999, 1e-8, 0.01)
+        w, m, v = mlp.adamw(cur, m, v, g, step, 1e-3, 0.9, 0.999, 1e-8, 0.01)
+        np.testing.assert_allclose(net.get_params(), w, rtol=1e-5, atol=1e-7)
+        w = net.get_params().astype(np.float64)
+
+
+def test_training_fits_a_smooth_map():
+    import torch
+
+    from paper_2109_04469_amd import Mlp
+
+    rng = np.random.default_rng(5)
+    n = 256
+    x = rng.uniform(-1, 1, size=(n, 6)).astype(np.float32)
+    grid = np.linspace(0, 1, 32)
+    t = (np.sin(np.outer(x[:, 0] + 0.5 * x[:, 1], 3 * grid)) + x[:, 2:3] * grid).astype(np.float32)
+    from oracle import mlp
+
+    dims = mlp.dims_of(6, 128, 3, 32)
+    p = np.zeros(mlp.num_params(dims))
+    for (W, b) in mlp.unpack(p, dims):
+        W[...] = rng.normal(scale=np.sqrt(2.0 / W.shape[1]), size=W.shape)
+    net = Mlp(6, 128, 3, 32, n)
+    net.set_params(p.astype(np.float32))
+    xd = torch.as_tensor(x).cuda()
+    td = torch.as_tensor(t).cuda()
+    net.grad(xd, td)
+    first = net.loss()
+    for _ in range(400):
+        net.train_step(xd, td, 2e-3)
+    torch.cuda.synchronize()
+    net.grad(xd, td)
+    assert net.loss() < 0.05 * first
+
+
+def test_load_profile_matches_oracle():
+    import oracle
+
+    from paper_2109_04469_amd import Discharge
+    from pic_inputs import workloads, xsec
+
+    w = workloads.get("c1_small")
+    p = dict(w["params"])
+    d = Discharge(p, xsec.argon_synthetic())
+    L = p["gap_m"]
+    rng = np.random.default_rng(3)
+    npts = 128
+    dens = np.exp(rng.normal(size=npts).cumsum() * 0.1)
+    dens[[0, -1]] = 0.0
+    temp = 2.0 + rng.uniform(0, 3, size=npts)
+    for sp, m, n in ((0, ME, 9000), (1, 39.948 * 1.66053906660e-27, 7777)):
+        d.load_profile(sp, n, dens, temp, step=0)
+        g = d.get_state(sp)
+        o = oracle.load_profile(dens, temp, L, QE / m, p["seed"], p["run"], sp, n)
+        assert np.array_equal(g[0], o[0]), "positions"
+        for k in (1, 2, 3):
+            np.testing.assert_allclose(g[k], o[k], rtol=1e-12, atol=1e-12 * np.abs(o[k]).max())
+    # the loaded state steps like any other
+    d.step(5)
+    assert d.sync() == 0
