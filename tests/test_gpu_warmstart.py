@@ -151,3 +151,18 @@ def test_load_profile_matches_oracle():
     # the loaded state steps like any other
     d.step(5)
     assert d.sync() == 0
+
+
+def test_warm_start_pipeline_small():
+    # the whole study at toy size: cold runs of a batch, training, warm
+    # loads from the predictions, and the convergence bookkeeping
+    from paper_2109_04469_amd import warmstart
+
+    data = warmstart.generate(n_train=6, n_test=2, cycles=40, avg_windows=2, seed=1)
+    assert data["x"].shape == (8, 6) and data["y"].shape == (8, warmstart.N_OUT)
+    assert not data["failed"].any()
+    assert np.all(np.isfinite(data["y"]))
+    res = warmstart.evaluate(data, warm_cycles=20, train_steps=50)
+    assert res["n_test"] == 2 and all(res["warm_loaded"])
+    assert len(res["initial_rel_l2_n_i"]["warm"]) == 2
+    assert res["train_loss"][-1][1] < res["train_loss"][0][1]
