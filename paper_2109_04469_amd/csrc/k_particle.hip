@@ -923,25 +923,6 @@ hipError_t launch_tail(int species, const FieldArgs& f, const PartArgs& a, int r
 // discharge at the boundaries, so that small discharges share the chip
 // instead of each leaving most of it idle.
 
-// Exclusive prefix sums of v (one value per thread, threads at or beyond n
-// hold none) into out[0..n], out[n] being the total. NT threads, n <= NT.
-// Ends with a barrier.
-template <int NT>
-__device__ __forceinline__ void block_exclusive(int64_t v, int n, int64_t* out, int64_t* s_w) {
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wave = tid / kWave;
-  if (tid >= n) v = 0;
-  const int64_t inc = wave_incl_scan<int64_t>(v);
-  if (lane == kWave - 1) s_w[wave] = inc;
-  __syncthreads();
-  int64_t off = 0;
-  for (int w = 0; w < wave; ++w) off += s_w[w];
-  if (tid < n) out[tid] = off + inc - v;
-  if (tid == NT - 1) out[n] = off + inc;
-  __syncthreads();
-}
-
 // Slots of a particle pass of discharge a: [0, n_push) are pushed and
 // [n_push, n_tot) carried, clamped to the capacity.
 template <int SP>

@@ -24,18 +24,23 @@ __device__ __forceinline__ void chunk_range(int64_t n, int nblocks, int b, int64
   if (lo > n) lo = n;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_count(SortArgs a) {
-  extern __shared__ uint32_t sh[];
+// Chunk b of a's input: per-key counts, written key-major.
+__device__ __forceinline__ void sort_count_block(const SortArgs& a, int b, uint32_t* sh) {
   const int nkeys = a.nx - 1;
   for (int k = threadIdx.x; k < nkeys; k += kSortThreads) sh[k] = 0u;
   __syncthreads();
   int64_t lo, hi;
-  chunk_range(min(*a.count, a.cap), a.nblocks, blockIdx.x, lo, hi);
+  chunk_range(min(*a.count, a.cap), a.nblocks, b, lo, hi);
   for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads)
     atomicAdd(&sh[cell_key(a.sx[i], a.inv_dx, a.nx)], 1u);
   __syncthreads();
   for (int k = threadIdx.x; k < nkeys; k += kSortThreads)
-    a.cnt[(size_t)k * a.nblocks + blockIdx.x] = sh[k];
+    a.cnt[(size_t)k * a.nblocks + b] = sh[k];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_count(SortArgs a) {
+  extern __shared__ uint32_t sh[];
+  sort_count_block(a, blockIdx.x, sh);
 }
 
 // Exclusive scan of the nkeys * nblocks counters in place, in three
@@ -51,11 +56,10 @@ __device__ __forceinline__ void seg_range(int64_t total, int seg, int64_t& lo, i
   if (lo > total) lo = total;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_scan_reduce(SortArgs a) {
-  __shared__ uint32_t s_w[kSortThreads / kWave];
+__device__ __forceinline__ void scan_reduce_seg(const SortArgs& a, int seg, uint32_t* s_w) {
   const int64_t total = (int64_t)(a.nx - 1) * a.nblocks;
   int64_t lo, hi;
-  seg_range(total, blockIdx.x, lo, hi);
+  seg_range(total, seg, lo, hi);
   uint32_t sum = 0;
   for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads) sum += a.cnt[i];
   sum = wave_sum<unsigned int>(sum);
@@ -64,12 +68,16 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_reduce(SortArgs a) {
   if (threadIdx.x == 0) {
     uint32_t t = 0;
     for (int w = 0; w < kSortThreads / kWave; ++w) t += s_w[w];
-    a.seg[blockIdx.x] = t;
+    a.seg[seg] = t;
   }
 }
 
-__global__ __launch_bounds__(kScanSegs) void k_scan_top(SortArgs a) {
-  __shared__ uint32_t s_w[kScanSegs / kWave];
+__global__ __launch_bounds__(kSortThreads) void k_scan_reduce(SortArgs a) {
+  __shared__ uint32_t s_w[kSortThreads / kWave];
+  scan_reduce_seg(a, blockIdx.x, s_w);
+}
+
+__device__ __forceinline__ void scan_top_all(const SortArgs& a, uint32_t* s_w) {
   const uint32_t v = a.seg[threadIdx.x];
   const uint32_t inc = wave_incl_scan<unsigned int>(v);
   if ((threadIdx.x & (kWave - 1)) == kWave - 1) s_w[threadIdx.x / kWave] = inc;
@@ -79,16 +87,20 @@ __global__ __launch_bounds__(kScanSegs) void k_scan_top(SortArgs a) {
   a.seg[threadIdx.x] = base + inc - v;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_scan_down(SortArgs a) {
-  __shared__ uint32_t s_w[kSortThreads / kWave];
+__global__ __launch_bounds__(kScanSegs) void k_scan_top(SortArgs a) {
+  __shared__ uint32_t s_w[kScanSegs / kWave];
+  scan_top_all(a, s_w);
+}
+
+__device__ __forceinline__ void scan_down_seg(const SortArgs& a, int seg, uint32_t* s_w) {
   const int64_t total = (int64_t)(a.nx - 1) * a.nblocks;
   int64_t lo, hi;
-  seg_range(total, blockIdx.x, lo, hi);
+  seg_range(total, seg, lo, hi);
   lo = uniform64(lo);
   hi = uniform64(hi);
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  uint32_t run = a.seg[blockIdx.x];
+  uint32_t run = a.seg[seg];
   for (int64_t b0 = lo; b0 < hi; b0 += kSortThreads) {
     const int64_t i = b0 + threadIdx.x;
     const uint32_t v = i < hi ? a.cnt[i] : 0u;
@@ -106,20 +118,24 @@ __global__ __launch_bounds__(kSortThreads) void k_scan_down(SortArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs a) {
-  extern __shared__ uint32_t off[];
-  __shared__ uint32_t s_base[kSortThreads / kWave][kWave];
+__global__ __launch_bounds__(kSortThreads) void k_scan_down(SortArgs a) {
+  __shared__ uint32_t s_w[kSortThreads / kWave];
+  scan_down_seg(a, blockIdx.x, s_w);
+}
+
+__device__ __forceinline__ void sort_scatter_block(const SortArgs& a, int b, uint32_t* off,
+                                                   uint32_t (*s_base)[kWave]) {
   const int nkeys = a.nx - 1;
   const int wave = threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   for (int k = threadIdx.x; k < nkeys; k += kSortThreads)
-    off[k] = a.cnt[(size_t)k * a.nblocks + blockIdx.x];
+    off[k] = a.cnt[(size_t)k * a.nblocks + b];
   __syncthreads();
   int64_t lo, hi;
   const int64_t n = min(uniform64(*a.count), a.cap);
   // the rebuilt pool holds exactly the n sorted slots
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.pool_n = n;
-  chunk_range(n, a.nblocks, blockIdx.x, lo, hi);
+  if (b == 0 && threadIdx.x == 0) *a.pool_n = n;
+  chunk_range(n, a.nblocks, b, lo, hi);
   lo = uniform64(lo);
   hi = uniform64(hi);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
@@ -165,6 +181,85 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs a) {
     }
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs a) {
+  extern __shared__ uint32_t off[];
+  __shared__ uint32_t s_base[kSortThreads / kWave][kWave];
+  sort_scatter_block(a, blockIdx.x, off, s_base);
+}
+
+// ---------------------------------------------------------------------------
+// Batched sorts: n independent jobs (one species of one discharge each, with
+// their own counters) in one launch per kernel. Count and scatter lay the
+// jobs' chunk blocks end to end; the scan kernels take kScanSegs blocks
+// (or one) per job.
+
+// The job of this workgroup among jobs whose block counts are nb(j), and
+// the workgroup's block within it.
+__device__ __forceinline__ void job_block(const SortArgs* __restrict__ args, int n, int& job,
+                                          int& b) {
+  __shared__ int64_t s_bs[kMaxBatch + 1];
+  __shared__ int64_t s_w[kSortThreads / kWave];
+  block_exclusive<kSortThreads>(threadIdx.x < (unsigned)n ? args[threadIdx.x].nblocks : 0, n, s_bs,
+                                s_w);
+  const int64_t g = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_bs[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  job = uniform32(lo);
+  b = uniform32((int)(g - s_bs[lo]));
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_count_b(const SortArgs* __restrict__ args,
+                                                                int n) {
+  extern __shared__ uint32_t sh[];
+  int job, b;
+  job_block(args, n, job, b);
+  sort_count_block(args[job], b, sh);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_scan_reduce_b(const SortArgs* __restrict__ args) {
+  __shared__ uint32_t s_w[kSortThreads / kWave];
+  const int job = blockIdx.x / kScanSegs;
+  scan_reduce_seg(args[job], blockIdx.x % kScanSegs, s_w);
+}
+
+__global__ __launch_bounds__(kScanSegs) void k_scan_top_b(const SortArgs* __restrict__ args) {
+  __shared__ uint32_t s_w[kScanSegs / kWave];
+  scan_top_all(args[blockIdx.x], s_w);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_scan_down_b(const SortArgs* __restrict__ args) {
+  __shared__ uint32_t s_w[kSortThreads / kWave];
+  const int job = blockIdx.x / kScanSegs;
+  scan_down_seg(args[job], blockIdx.x % kScanSegs, s_w);
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter_b(const SortArgs* __restrict__ args,
+                                                                  int n) {
+  extern __shared__ uint32_t off[];
+  __shared__ uint32_t s_base[kSortThreads / kWave][kWave];
+  int job, b;
+  job_block(args, n, job, b);
+  sort_scatter_block(args[job], b, off, s_base);
+}
+
+hipError_t launch_batch_sort(const SortArgs* args, int n, int64_t total_blocks, int nx_max,
+                             hipStream_t s) {
+  if (n < 1 || n > kMaxBatch || total_blocks < 1 || nx_max < 3) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(nx_max - 1) * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_sort_count_b, dim3((unsigned)total_blocks), dim3(kSortThreads), lds, s, args,
+                     n);
+  hipLaunchKernelGGL(k_scan_reduce_b, dim3(n * kScanSegs), dim3(kSortThreads), 0, s, args);
+  hipLaunchKernelGGL(k_scan_top_b, dim3(n), dim3(kScanSegs), 0, s, args);
+  hipLaunchKernelGGL(k_scan_down_b, dim3(n * kScanSegs), dim3(kSortThreads), 0, s, args);
+  hipLaunchKernelGGL(k_sort_scatter_b, dim3((unsigned)total_blocks), dim3(kSortThreads), lds, s,
+                     args, n);
+  return hipGetLastError();
 }
 
 // The pool in slot order without moving the slots: entry i of the new pool

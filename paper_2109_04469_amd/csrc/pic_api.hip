@@ -475,10 +475,12 @@ size_t batch_step_bytes(int n) {
   // particle blocks: electron passes, electron passes of ion steps (their
   // queued slots run before the ions), ion passes, and the electron passes
   // whose queued slots run in the tail
+  // plus the sorts of both species due after the step
   const size_t f = (size_t)n * sizeof(FieldArgs);
   const size_t a = (size_t)n * sizeof(PartArgs);
+  const size_t so = (size_t)n * sizeof(SortArgs);
   auto al = [](size_t v) { return (v + kBatchArrayAlign - 1) / kBatchArrayAlign * kBatchArrayAlign; };
-  return 2 * al(f) + 4 * al(a);
+  return 2 * al(f) + 4 * al(a) + 2 * al(so);
 }
 
 int batch_chunk_steps(int n) {
@@ -912,7 +914,9 @@ int pic_batch_step(pic_batch* b, int64_t n_steps) {
     const PartArgs* er;
     const PartArgs* ia;
     const PartArgs* t0;
-    int nff, nem, nion, nt0;
+    const SortArgs* so[2];  // sorts of each species due after the step
+    int nff, nem, nion, nt0, nso;
+    int64_t so_blocks;
     bool tail;
   };
   struct Post {
@@ -949,6 +953,9 @@ int pic_batch_step(pic_batch* b, int64_t n_steps) {
       const size_t o_ff = take(n * sizeof(FieldArgs)), o_fn = take(n * sizeof(FieldArgs));
       const size_t o_ed = take(n * sizeof(PartArgs)), o_er = take(n * sizeof(PartArgs));
       const size_t o_ia = take(n * sizeof(PartArgs)), o_t0 = take(n * sizeof(PartArgs));
+      const size_t o_s0 = take(n * sizeof(SortArgs)), o_s1 = take(n * sizeof(SortArgs));
+      SortArgs* s0 = reinterpret_cast<SortArgs*>(H + o_s0);
+      SortArgs* s1 = reinterpret_cast<SortArgs*>(H + o_s1);
       FieldArgs* ff = reinterpret_cast<FieldArgs*>(H + o_ff);
       FieldArgs* fn = reinterpret_cast<FieldArgs*>(H + o_fn);
       PartArgs* ed = reinterpret_cast<PartArgs*>(H + o_ed);
@@ -972,7 +979,13 @@ int pic_batch_step(pic_batch* b, int64_t n_steps) {
         } else {
           t0[L.nt0++] = q.ae;
         }
-        if (q.post) posts.push_back(Post{k, i, q});
+        if (q.post == 1) {
+          s0[L.nso] = q.sa[0];
+          s1[L.nso++] = q.sa[1];
+          L.so_blocks += q.sa[0].nblocks;
+        } else if (q.post) {
+          posts.push_back(Post{k, i, q});
+        }
       }
       L.ff = reinterpret_cast<const FieldArgs*>(D + o_ff);
       L.fn = reinterpret_cast<const FieldArgs*>(D + o_fn);
@@ -980,6 +993,8 @@ int pic_batch_step(pic_batch* b, int64_t n_steps) {
       L.er = reinterpret_cast<const PartArgs*>(D + o_er);
       L.ia = reinterpret_cast<const PartArgs*>(D + o_ia);
       L.t0 = reinterpret_cast<const PartArgs*>(D + o_t0);
+      L.so[0] = reinterpret_cast<const SortArgs*>(D + o_s0);
+      L.so[1] = reinterpret_cast<const SortArgs*>(D + o_s1);
       steps.push_back(L);
     }
     HIP_TRY(hipMemcpyAsync(D, H, off, hipMemcpyHostToDevice, s));
@@ -1006,6 +1021,12 @@ int pic_batch_step(pic_batch* b, int64_t n_steps) {
       } else {
         if (L.nt0) HIP_TRY(launch_batch_pass(2, 0, false, L.t0, L.nt0, c, s));
         if (L.nion) HIP_TRY(launch_batch_pass(2, 1, false, L.ia, L.nion, c, s));
+      }
+      // cell sorts: species 0 of every due discharge, then species 1 (the
+      // two species of a discharge share its sort counters)
+      if (L.nso) {
+        HIP_TRY(launch_batch_sort(L.so[0], L.nso, L.so_blocks, c.nx_max, s));
+        HIP_TRY(launch_batch_sort(L.so[1], L.nso, L.so_blocks, c.nx_max, s));
       }
       for (; pi < posts.size() && posts[pi].step == k; ++pi) {
         const int st = launch_post(b->hs[posts[pi].discharge], posts[pi].q, s);

@@ -170,6 +170,10 @@ hipError_t launch_batch_tail(int species, const FieldArgs* f, int nf, const Part
                              int rare_blocks, hipStream_t s);
 hipError_t launch_batch_field(const FieldArgs* f, int n, hipStream_t s);
 hipError_t launch_sort(const SortArgs& a, hipStream_t s);
+// n independent sorts (args in device memory, each with its own counters);
+// total_blocks = the sum of their nblocks, nx_max the largest nx
+hipError_t launch_batch_sort(const SortArgs* args, int n, int64_t total_blocks, int nx_max,
+                             hipStream_t s);
 // pool repacked in slot order (no reordering of the slots)
 hipError_t launch_repack(const SortArgs& a, hipStream_t s);
 // id[i] = i for i < *count
