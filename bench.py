@@ -29,6 +29,9 @@ sweep: the batched-sweep workload (64 seeded independent discharges of
 uneven size), advanced one discharge after the other, on one stream each,
 and as one batch with one launch per pass for all; throughputs, speedups
 over the one-after-the-other run, and whether all three agree bitwise.
+warm_start (with --warm-start only, about 10 GPU-minutes): RF cycles to
+convergence of 16 held-out discharges started from the network's predicted
+profiles vs from a uniform plasma (paper_2109_04469_amd.warmstart).
 """
 import argparse
 import json
@@ -202,6 +205,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched-sweep workload")
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the batched-sweep workload and print its JSON object")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="also run the warm-start study (about 10 GPU-minutes: 112 cold runs of "
+                         "2000 RF cycles, training, 16 warm runs of 1500 cycles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs one discharge on one GPU; --gpus {args.gpus} is not supported "
@@ -333,6 +339,22 @@ def main():
         del d
         torch.cuda.empty_cache()
         out["sweep"] = sweep_measurement(torch, args.sweep_steps, log=log)
+    out["warm_start"] = None
+    if args.warm_start:
+        from paper_2109_04469_amd import warmstart
+
+        log("[bench] warm-start study: cold runs")
+        data = warmstart.generate()
+        log("[bench] warm-start study: training and warm runs")
+        res = warmstart.evaluate(data, warm_cycles=1500)
+        out["warm_start"] = {
+            "workload": "warm-start family (seed 0): 96 training + 16 held-out discharges",
+            "metric": "RF cycles until the 10-cycle-averaged ion density stays within delta of the "
+                      "converged cold-run reference",
+            "delta_0.1": res["delta_0.1"], "delta_0.05": res["delta_0.05"],
+            "prediction_rel_l2_n_i": res["prediction_rel_l2_n_i"],
+            "train_seconds": res["train_seconds"], "warm_run_seconds": res["warm_run_seconds"],
+        }
     if not args.no_cpu:
         log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(w, init, xs, args.cpu_steps)
