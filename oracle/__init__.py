@@ -2,8 +2,10 @@
 
 TEST INFRASTRUCTURE ONLY: imported by tests/, by __graft_entry__.smoke()
 and by the CPU-baseline leg of bench.py, never by the simulation package.
-The arithmetic lives in plain C (pic_oracle.c, philox.c); this module only
-builds that library with gcc and marshals numpy arrays to it.
+The step's arithmetic lives in plain C (pic_oracle.c, philox.c,
+warm_oracle.c); this module builds that library with gcc and marshals numpy
+arrays to it, and writes out in numpy the few closed-form diagnostics derived
+from its averages (monitors) and the warm-start network (mlp.py).
 """
 from __future__ import annotations
 
@@ -77,6 +79,7 @@ def lib():
         L.ora_thomas.argtypes = [ctypes.c_int64, d, d, d, d, d]
         L.ora_poisson.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, d, d]
         L.ora_efield.argtypes = [ctypes.c_int32, ctypes.c_double, d, d, d]
+        L.ora_wall_raw.argtypes = [P, i64p, i64p, d, i64p, i64p, i64p, d]
         L.ora_load_profile.argtypes = [d, d, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                        ctypes.c_int64, d, d, d, d]
@@ -170,6 +173,28 @@ def efield(nx, dx, rho, phi):
     E = np.zeros(nx)
     lib().ora_efield(nx, dx, _dp(rho), _dp(phi), _dp(E))
     return E
+
+
+def monitors(moments, params, p_coll):
+    """Stability and accuracy monitors of Sec. 3.5 from time averages:
+    omega_pe dt with the largest averaged electron density, the Debye length
+    sqrt(eps0 T_e / (e n_e)) at L/2 with T_e = (2/3) <eps> (eV), dx / lambda_D
+    and the superparticles per Debye length n_e A lambda_D / W at L/2 (the
+    middle grid point, or the two middle points combined)."""
+    eps0, qe, me = 8.8541878128e-12, 1.602176634e-19, 9.1093837015e-31
+    ne = np.asarray(moments["n_e"])
+    nx = ne.size
+    j0, j1 = (nx - 1) // 2, nx // 2
+    nc = 0.5 * (ne[j0] + ne[j1])
+    em = np.asarray(moments["mean_energy_e"])
+    ec = 0.5 * (em[j0] + em[j1])
+    dt = 1.0 / (params["rf_freq_hz"] * params["steps_per_cycle"])
+    dx = params["gap_m"] / params["n_cells"]
+    lam = np.sqrt(eps0 * (2.0 / 3.0) * ec / (qe * nc)) if nc > 0 else 0.0
+    return dict(omega_pe_dt=np.sqrt(ne.max() * qe * qe / (eps0 * me)) * dt, p_coll=tuple(p_coll),
+                n_e_max=ne.max(), n_e_center=nc, mean_energy_center_ev=ec, lambda_d_m=lam,
+                dx_over_lambda_d=dx / lam if lam > 0 else 0.0,
+                n_d=nc * params["area_m2"] * lam / params["weight"])
 
 
 def load_profile(dens, temp_ev, L, vfac, seed, run, species, n):
@@ -278,6 +303,43 @@ class Oracle:
 
     def measure(self, on=True):
         self.L.ora_measure(self.h, 1 if on else 0)
+
+    def wall_raw(self):
+        """Electrode arrivals since the last moments reset: hits, absorbed,
+        energy sums [species, wall], arrival histograms [species, wall, bin],
+        ionizations, measured steps and the bins' upper edges per species."""
+        nb = int(self.params["eepf_bins"])
+        hits = np.zeros(4, np.int64)
+        absd = np.zeros(4, np.int64)
+        esum = np.zeros(4)
+        hist = np.zeros(4 * nb, np.int64)
+        ion = ctypes.c_int64()
+        st = ctypes.c_int64()
+        emax = np.zeros(2)
+        self.L.ora_wall_raw(self.h, _ip(hits), _ip(absd), _dp(esum), _ip(hist), ctypes.byref(ion),
+                            ctypes.byref(st), _dp(emax))
+        return dict(hits=hits.reshape(2, 2), absorbed=absd.reshape(2, 2), esum=esum.reshape(2, 2),
+                    hist=hist.reshape(2, 2, nb), ionizations=ion.value, steps=st.value, emax=emax)
+
+    def wall_moments(self):
+        """Fluxes per m^2 per s over the measured steps, mean impact energies
+        and flux-energy distributions normalised to unit integral (Sec. 3.3)."""
+        r = self.wall_raw()
+        p = self.params
+        dt = 1.0 / (p["rf_freq_hz"] * p["steps_per_cycle"])
+        per = p["weight"] / (p["area_m2"] * r["steps"] * dt) if r["steps"] else 0.0
+        nb = r["hist"].shape[2]
+        fedf = np.zeros((2, 2, nb))
+        for k in range(2):
+            de = r["emax"][k] / nb
+            for w in range(2):
+                tot = r["hist"][k, w].sum()
+                if tot:
+                    fedf[k, w] = r["hist"][k, w] / (tot * de)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            mean = np.where(r["hits"] > 0, r["esum"] / np.maximum(r["hits"], 1), 0.0)
+        return dict(flux=per * r["hits"], absorbed_flux=per * r["absorbed"], mean_energy_ev=mean,
+                    fedf=fedf, ionization_rate=per * r["ionizations"], raw=r)
 
     def moments(self, reset=False):
         nx = self.nx

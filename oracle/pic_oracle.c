@@ -94,6 +94,11 @@ typedef struct {
   int64_t msteps;
   double *acc_ne, *acc_ni, *acc_ew, *acc_w;
   int64_t *eepf_h;
+  /* electrode arrivals while measuring, [species][wall], wall 0 at x = 0 */
+  int64_t wall_hits[2][2], wall_abs[2][2], ioniz_meas;
+  double wall_esum[2][2];
+  int64_t *fedf[2];  /* [wall][eepf_bins] per species */
+  double fedf_emax[2], ek[2];
   int64_t counters[NCOUNT];
   uint8_t *codes[2];
   int64_t ncodes[2];
@@ -337,6 +342,14 @@ ora_sim* ora_create(const ora_params* p, const double* sig_e0, const double* sig
   s->acc_ew = dalloc(s->nx);
   s->acc_w = dalloc(s->nx);
   s->eepf_h = (int64_t*)calloc((size_t)p->eepf_bins, sizeof(int64_t));
+  /* arrival energy bins: the EEPF range for electrons; ions gain at most
+   * about the peak sheath voltage: 1.25 phi_0, at least 10 eV */
+  s->fedf_emax[0] = p->eepf_emax_ev;
+  s->fedf_emax[1] = 1.25 * p->rf_voltage_v > 10.0 ? 1.25 * p->rf_voltage_v : 10.0;
+  for (int k = 0; k < 2; k++) {
+    s->fedf[k] = (int64_t*)calloc((size_t)(2 * p->eepf_bins), sizeof(int64_t));
+    s->ek[k] = 0.5 * s->mass[k] / Q_E;
+  }
   return s;
 }
 
@@ -360,6 +373,8 @@ void ora_free(ora_sim* s) {
   free(s->acc_ew);
   free(s->acc_w);
   free(s->eepf_h);
+  free(s->fedf[0]);
+  free(s->fedf[1]);
   free(s);
 }
 
@@ -449,7 +464,32 @@ void ora_moments(ora_sim* s, double* ne, double* ni, double* emean, double* eepf
     memset(s->acc_ew, 0, sizeof(double) * (size_t)nx);
     memset(s->acc_w, 0, sizeof(double) * (size_t)nx);
     memset(s->eepf_h, 0, sizeof(int64_t) * (size_t)s->p.eepf_bins);
+    for (int k = 0; k < 2; k++) memset(s->fedf[k], 0, sizeof(int64_t) * (size_t)(2 * s->p.eepf_bins));
+    memset(s->wall_hits, 0, sizeof(s->wall_hits));
+    memset(s->wall_abs, 0, sizeof(s->wall_abs));
+    memset(s->wall_esum, 0, sizeof(s->wall_esum));
+    s->ioniz_meas = 0;
   }
+}
+
+/* Electrode diagnostics since the last reset: arrivals, absorptions and
+ * impact-energy sums [species][wall] (flattened 2 x 2), the raw arrival
+ * histograms [species][wall][eepf_bins], the ionizations and the measured
+ * steps. */
+void ora_wall_raw(const ora_sim* s, int64_t* hits, int64_t* absorbed, double* esum, int64_t* hist,
+                  int64_t* ioniz, int64_t* steps, double* emax) {
+  for (int k = 0; k < 2; k++)
+    for (int w = 0; w < 2; w++) {
+      hits[2 * k + w] = s->wall_hits[k][w];
+      absorbed[2 * k + w] = s->wall_abs[k][w];
+      esum[2 * k + w] = s->wall_esum[k][w];
+    }
+  for (int k = 0; k < 2; k++)
+    memcpy(hist + (size_t)k * 2 * s->p.eepf_bins, s->fedf[k], sizeof(int64_t) * (size_t)(2 * s->p.eepf_bins));
+  *ioniz = s->ioniz_meas;
+  *steps = s->msteps;
+  emax[0] = s->fedf_emax[0];
+  emax[1] = s->fedf_emax[1];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -596,6 +636,16 @@ int ora_step(ora_sim* s, int64_t nsteps) {
           alive = 0;
           code |= 1;
         } else if (x < 0.0 || x > L) {
+          /* arrival at an electrode: count it, its impact energy and its
+           * energy bin (Sec. 3.3); absorption is added below */
+          int wall = x < 0.0 ? 0 : 1;
+          if (s->measuring) {
+            double eps = s->ek[sp] * (vx * vx + vy * vy + vz * vz);
+            s->wall_hits[sp][wall]++;
+            s->wall_esum[sp][wall] += eps;
+            int64_t b = (int64_t)(eps * ((double)p->eepf_bins / s->fedf_emax[sp]));
+            if (b >= 0 && b < p->eepf_bins) s->fedf[sp][(int64_t)wall * p->eepf_bins + b]++;
+          }
           double ub = u01(r0[0]);
           if (sp == 0) {
             if (ub < p->reflection) {
@@ -636,6 +686,7 @@ int ora_step(ora_sim* s, int64_t nsteps) {
               code |= 1;
             }
           }
+          if (s->measuring && !alive) s->wall_abs[sp][wall]++;
         }
         /* (6) null-collision Monte Carlo */
         int child = 0;
@@ -706,6 +757,7 @@ int ora_step(ora_sim* s, int64_t nsteps) {
                 plist_push(&ibirth, x, s->sig_g * n1, s->sig_g * n2, s->sig_g * n3);
                 code |= 4 << 3;
                 s->counters[C_E_ION]++;
+                if (s->measuring) s->ioniz_meas++;
               } else {
                 code |= 1 << 3;
               }
