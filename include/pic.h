@@ -155,6 +155,49 @@ typedef struct pic_moments_out {
   int64_t  steps_averaged;
 } pic_moments_out;
 
+/* Electrode diagnostics over the measured steps (Sec. 3.3: the mean ion
+ * flux to the electrodes and the flux-energy distributions of electrons and
+ * ions arriving there). Index [s][w]: species s (0 e-, 1 Ar+), electrode w
+ * (0: x = 0, driven; 1: x = L, grounded). An arrival is a particle that
+ * leaves the gap through the electrode in a push; electrons that are then
+ * reflected count as arrivals but not as absorbed. Its impact energy is
+ * (m/2)|v|^2 with the pushed velocity. fedf[s][w]: caller-owned host arrays
+ * of fedf_bins values (or NULL), f(eps) in eV^-1 normalised so that the sum
+ * over bins of f d(eps) is 1 (arrivals above fedf_emax_ev count in the
+ * fluxes and mean energies but not in f); bins of width fedf_emax_ev[s] /
+ * fedf_bins, fedf_emax_ev = eepf_emax_ev for electrons and
+ * max(1.25 phi_0, 10 eV) for ions, fedf_bins = eepf_bins. */
+typedef struct pic_wall_out {
+  int64_t  arrivals[2][2];
+  int64_t  absorbed[2][2];
+  double   flux[2][2];            /* arrivals per m^2 per s                    */
+  double   absorbed_flux[2][2];   /* absorptions per m^2 per s                 */
+  double   mean_energy_ev[2][2];  /* mean impact energy                        */
+  double*  fedf[2][2];
+  double   fedf_emax_ev[2];
+  int32_t  fedf_bins;
+  int64_t  ionizations;           /* electron-impact ionizations, same steps   */
+  double   ionization_rate;       /* per m^2 per s: in a steady state it equals
+                                     the ion flux absorbed at both electrodes  */
+  int64_t  steps_averaged;
+} pic_wall_out;
+
+/* Stability and accuracy monitors of Sec. 3.5 from the time averages. */
+typedef struct pic_monitors {
+  double  omega_pe_dt;           /* sqrt(e^2 n_max / (eps0 m_e)) dt, n_max the
+                                    largest time-averaged electron density     */
+  double  p_coll[2];             /* 1 - exp(-nu_max dt_s) per species          */
+  double  n_e_max;
+  double  n_e_center;            /* time-averaged n_e at L/2, m^-3             */
+  double  mean_energy_center_ev; /* CIC-weighted mean electron energy at L/2   */
+  double  lambda_d_m;            /* sqrt(eps0 T_e / (e n_e)) at L/2,
+                                    T_e = (2/3) <eps> in eV                    */
+  double  dx_over_lambda_d;
+  double  n_d;                   /* superparticles per Debye length at L/2:
+                                    n_e A lambda_D / W                         */
+  int64_t steps_averaged;
+} pic_monitors;
+
 typedef struct pic_handle pic_handle;
 
 /* Size of the single device workspace for parameter set *p (capacities, grid,
@@ -219,6 +262,17 @@ int pic_measure(pic_handle* h, int on);
 /* Reads the time-averaged moments; reset != 0 clears the accumulators
  * afterwards. Synchronises. */
 int pic_moments(pic_handle* h, pic_moments_out* out, int reset);
+
+/* Electrode fluxes, impact energies and flux-energy distributions over the
+ * steps measured since the last pic_moments reset (which clears these too).
+ * Synchronises. */
+int pic_wall_moments(pic_handle* h, pic_wall_out* out);
+
+/* omega_pe dt, P_coll, Debye length, dx / lambda_D and the superparticles
+ * per Debye length (Sec. 3.5) from the current time averages. At the centre
+ * L/2: the middle grid point, or the mean of the two middle points for an
+ * even number of points. Synchronises. */
+int pic_get_monitors(pic_handle* h, pic_monitors* out);
 
 /* Copies the PIC_NCOUNTERS event counters (host int64 array). Synchronises. */
 int pic_get_counters(pic_handle* h, int64_t* counters);

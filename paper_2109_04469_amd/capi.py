@@ -63,6 +63,29 @@ class PicMomentsOut(ctypes.Structure):
     ]
 
 
+_D2 = ctypes.c_double * 2
+_I2 = ctypes.c_int64 * 2
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+class PicWallOut(ctypes.Structure):
+    _fields_ = [
+        ("arrivals", _I2 * 2), ("absorbed", _I2 * 2), ("flux", _D2 * 2), ("absorbed_flux", _D2 * 2),
+        ("mean_energy_ev", _D2 * 2), ("fedf", (_DP * 2) * 2), ("fedf_emax_ev", _D2),
+        ("fedf_bins", ctypes.c_int32), ("ionizations", ctypes.c_int64),
+        ("ionization_rate", ctypes.c_double), ("steps_averaged", ctypes.c_int64),
+    ]
+
+
+class PicMonitors(ctypes.Structure):
+    _fields_ = [
+        ("omega_pe_dt", ctypes.c_double), ("p_coll", _D2), ("n_e_max", ctypes.c_double),
+        ("n_e_center", ctypes.c_double), ("mean_energy_center_ev", ctypes.c_double),
+        ("lambda_d_m", ctypes.c_double), ("dx_over_lambda_d", ctypes.c_double),
+        ("n_d", ctypes.c_double), ("steps_averaged", ctypes.c_int64),
+    ]
+
+
 _lib = None
 
 
@@ -109,6 +132,8 @@ def load():
     L.pic_get_field.argtypes = [P, P, P, P, P, P]
     L.pic_measure.argtypes = [P, ctypes.c_int]
     L.pic_moments.argtypes = [P, ctypes.POINTER(PicMomentsOut), ctypes.c_int]
+    L.pic_wall_moments.argtypes = [P, ctypes.POINTER(PicWallOut)]
+    L.pic_get_monitors.argtypes = [P, ctypes.POINTER(PicMonitors)]
     L.pic_get_counters.argtypes = [P, P]
     L.pic_get_decisions.argtypes = [P, ctypes.c_int, P, i64, ctypes.POINTER(i64)]
     L.pic_get_derived.argtypes = [P, ctypes.POINTER(PicDerived)]
@@ -123,7 +148,7 @@ def load():
     L.pic_selftest_copy.argtypes = [P, P, i64, P]
     for name in ("pic_workspace_bytes", "pic_init", "pic_set_state", "pic_get_state", "pic_step",
                  "pic_step_many", "pic_batch_workspace_bytes", "pic_batch_create", "pic_batch_step",
-                 "pic_load_profile", "pic_mlp_workspace_bytes", "pic_mlp_init", "pic_mlp_num_params",
+                 "pic_load_profile", "pic_wall_moments", "pic_get_monitors", "pic_mlp_workspace_bytes", "pic_mlp_init", "pic_mlp_num_params",
                  "pic_mlp_set_params", "pic_mlp_get_params", "pic_mlp_forward", "pic_mlp_grad",
                  "pic_mlp_get_grad", "pic_mlp_get_loss", "pic_mlp_adam", "pic_mlp_train_step",
                  "pic_sync", "pic_set_field", "pic_get_field", "pic_measure", "pic_moments",

@@ -133,6 +133,23 @@ static_assert(kDGroups >= 1 && kTile % (4 * kDB) == 0, "a tile is whole runs of 
 // candidate: a small fraction of slots. x and vx are the pushed values and
 // are updated (reflection); the code, the number of own outputs and of
 // births are returned through c, o and b.
+// A particle of species SP reaching electrode `wall` (0: x = 0) with the
+// pushed velocity (vx and the pool's v_y, v_z): arrival count, absorption,
+// impact energy and its bin of the flux-energy distribution (Sec. 3.3).
+template <int SP>
+__device__ __forceinline__ void record_arrival(const PartArgs& a, int64_t slot, double vx, int wall,
+                                               bool absorbed) {
+  const uint32_t id = a.idin[slot];
+  const double vy = a.pvy[id], vz = a.pvz[id];
+  const double eps = a.ek_s * (vx * vx + vy * vy + vz * vz);
+  DevCtl* ctl = a.ctl;
+  atomicAdd(&ctl->wall_hits[SP][wall], 1ull);
+  if (absorbed) atomicAdd(&ctl->wall_absorbed[SP][wall], 1ull);
+  atomicAdd(&ctl->wall_esum[SP][wall], eps);
+  const int64_t bin = (int64_t)(eps * a.fedf_inv_de);
+  if (bin >= 0 && bin < a.nbins) atomicAdd(&a.fedf[(int64_t)wall * a.nbins + bin], 1ull);
+}
+
 template <int SP, bool MEASURE>
 __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long long* s_cnt,
                                             int64_t slot, bool cand, double& x, double& vx,
@@ -146,6 +163,8 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
     alive = false;
     c |= 1u;
   } else if (x < 0.0 || x > L) {
+    const int wall = x < 0.0 ? 0 : 1;
+    const double vx_hit = vx;
     const double ub = u01(draw(step, (uint32_t)slot, SP, 0, a.seed, a.run).x);
     if (SP == 0) {
       if (ub < a.p_wall) {
@@ -177,6 +196,7 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
         c |= 1u;
       }
     }
+    if (a.measure_walls) record_arrival<SP>(a, slot, vx_hit, wall, !alive);
   }
   if (alive && cand) {
     if (SP == 0) {
@@ -201,6 +221,7 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
         b = 1;
         mul = 2;
         atomicAdd(&s_cnt[C_E_ION], 1ull);
+        if (a.measure_walls) atomicAdd(&a.ctl->ioniz_meas, 1ull);
         deposit_global(a.dep_other, x, a.inv_dx, a.nx);
       }
       c |= proc << 3;

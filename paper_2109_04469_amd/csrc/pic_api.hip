@@ -38,9 +38,16 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 constexpr int kRepackSteps = 256;
 int64_t pool_capacity(int64_t cap) { return cap + (cap / 2 > 4096 ? cap / 2 : 4096); }
 
+// Upper edge of the ion arrival-energy bins: ions gain at most about the
+// peak sheath voltage, so 1.25 phi_0 (at least 10 eV).
+double fedf_ion_emax(double rf_voltage_v) {
+  const double e = 1.25 * rf_voltage_v;
+  return e > 10.0 ? e : 10.0;
+}
+
 struct Layout {
   size_t ctl, part[2][2][2], pid[2][2], pool[2][2][2], codes[2], tcnt[2], rq[2], dep_e[2], dep_i[2], rho, phi, E[2], cum[2], th_cp,
-      th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, sort_cnt, sort_seg, total;
+      th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, fedf[2], sort_cnt, sort_seg, total;
   int64_t max_tiles[2];
   int sort_blocks;
 };
@@ -108,6 +115,7 @@ Layout make_layout(const pic_params* p, const pic_xsec* xs) {
   L.acc_w = take((size_t)nx * 8);
   L.acc_ew = take((size_t)nx * 8);
   L.eepf = take((size_t)p->eepf_bins * 8);
+  for (int sp = 0; sp < 2; ++sp) L.fedf[sp] = take((size_t)2 * p->eepf_bins * 8);
   int64_t capmax = p->capacity[0] > p->capacity[1] ? p->capacity[0] : p->capacity[1];
   int sb = (int)((capmax + 16383) / 16384);
   if (sb < 1) sb = 1;
@@ -232,6 +240,10 @@ PartArgs particle_args(pic_handle* h, int sp, int parity) {
   a.codes = h->codes[sp];
   a.acc_ew = h->acc_ew;
   a.eepf = h->eepf;
+  a.fedf = h->fedf[sp];
+  a.ek_s = 0.5 * h->mass[sp] / kQe;
+  a.fedf_inv_de = (double)h->p.eepf_bins / h->fedf_emax[sp];
+  a.measure_walls = h->measuring;
   a.cap = h->p.capacity[sp];
   a.bcap = h->p.capacity[other];
   a.max_tiles = h->max_tiles[sp];
@@ -692,6 +704,9 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
   h->acc_w = reinterpret_cast<double*>(w + L.acc_w);
   h->acc_ew = reinterpret_cast<double*>(w + L.acc_ew);
   h->eepf = reinterpret_cast<unsigned long long*>(w + L.eepf);
+  for (int sp = 0; sp < 2; ++sp) h->fedf[sp] = reinterpret_cast<unsigned long long*>(w + L.fedf[sp]);
+  h->fedf_emax[0] = p->eepf_emax_ev;
+  h->fedf_emax[1] = fedf_ion_emax(p->rf_voltage_v);
   h->sort_cnt = reinterpret_cast<uint32_t*>(w + L.sort_cnt);
   h->sort_seg = reinterpret_cast<uint32_t*>(w + L.sort_seg);
   h->sort_blocks = L.sort_blocks;
@@ -1117,9 +1132,93 @@ int pic_moments(pic_handle* h, pic_moments_out* out, int reset) {
     HIP_TRY(hipMemsetAsync(h->acc_w, 0, nx * 8, h->stream));
     HIP_TRY(hipMemsetAsync(h->acc_ew, 0, nx * 8, h->stream));
     HIP_TRY(hipMemsetAsync(h->eepf, 0, nb * 8, h->stream));
+    for (int sp = 0; sp < 2; ++sp) HIP_TRY(hipMemsetAsync(h->fedf[sp], 0, (size_t)2 * nb * 8, h->stream));
+    HIP_TRY(hipMemsetAsync(h->ctl->wall_hits, 0,
+                           sizeof(h->ctl->wall_hits) + sizeof(h->ctl->wall_absorbed) +
+                               sizeof(h->ctl->wall_esum) + sizeof(h->ctl->ioniz_meas),
+                           h->stream));
     HIP_TRY(hipMemsetAsync(&h->ctl->msteps, 0, 8, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
   }
+  return latched(h);
+}
+
+int pic_wall_moments(pic_handle* h, pic_wall_out* out) {
+  if (!h || !out) return PIC_EINVAL;
+  const int nb = h->p.eepf_bins;
+  std::vector<unsigned long long> hist[2];
+  unsigned long long hits[2][2], absd[2][2], ioniz = 0;
+  double esum[2][2];
+  int64_t msteps = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    hist[sp].resize((size_t)2 * nb);
+    HIP_TRY(hipMemcpyAsync(hist[sp].data(), h->fedf[sp], (size_t)2 * nb * 8, hipMemcpyDeviceToHost,
+                           h->stream));
+  }
+  HIP_TRY(hipMemcpyAsync(hits, h->ctl->wall_hits, sizeof(hits), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(absd, h->ctl->wall_absorbed, sizeof(absd), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(esum, h->ctl->wall_esum, sizeof(esum), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(&ioniz, &h->ctl->ioniz_meas, 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(&msteps, &h->ctl->msteps, 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  // particles per m^2 per s over the measured time msteps * dt
+  const double per = msteps ? h->p.weight / (h->p.area_m2 * (double)msteps * h->dt) : 0.0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const double de = h->fedf_emax[sp] / (double)nb;
+    out->fedf_emax_ev[sp] = h->fedf_emax[sp];
+    for (int w = 0; w < 2; ++w) {
+      out->arrivals[sp][w] = (int64_t)hits[sp][w];
+      out->absorbed[sp][w] = (int64_t)absd[sp][w];
+      out->flux[sp][w] = per * (double)hits[sp][w];
+      out->absorbed_flux[sp][w] = per * (double)absd[sp][w];
+      out->mean_energy_ev[sp][w] = hits[sp][w] ? esum[sp][w] / (double)hits[sp][w] : 0.0;
+      double* f = out->fedf[sp][w];
+      if (!f) continue;
+      unsigned long long tot = 0;
+      for (int b = 0; b < nb; ++b) tot += hist[sp][(size_t)w * nb + b];
+      for (int b = 0; b < nb; ++b)
+        f[b] = tot ? (double)hist[sp][(size_t)w * nb + b] / ((double)tot * de) : 0.0;
+    }
+  }
+  out->fedf_bins = nb;
+  out->ionizations = (int64_t)ioniz;
+  out->ionization_rate = per * (double)ioniz;
+  out->steps_averaged = msteps;
+  return latched(h);
+}
+
+int pic_get_monitors(pic_handle* h, pic_monitors* out) {
+  if (!h || !out) return PIC_EINVAL;
+  const int nx = h->nx;
+  std::vector<double> ne(nx), w(nx), ew(nx);
+  int64_t msteps = 0;
+  HIP_TRY(hipMemcpyAsync(ne.data(), h->acc_ne, nx * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(w.data(), h->acc_w, nx * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(ew.data(), h->acc_ew, nx * 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(&msteps, &h->ctl->msteps, 8, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  out->steps_averaged = msteps;
+  out->p_coll[0] = h->pcoll[0];
+  out->p_coll[1] = h->pcoll[1];
+  double nmax = 0.0;
+  for (int j = 0; j < nx; ++j) {
+    ne[j] = msteps ? ne[j] / (double)msteps : 0.0;
+    nmax = ne[j] > nmax ? ne[j] : nmax;
+  }
+  // centre values: the middle node, or the mean of the two middle nodes
+  const int j0 = (nx - 1) / 2, j1 = nx / 2;
+  const double nc = 0.5 * (ne[j0] + ne[j1]);
+  const double e0 = w[j0] > 0.0 ? ew[j0] / w[j0] : 0.0;
+  const double e1 = w[j1] > 0.0 ? ew[j1] / w[j1] : 0.0;
+  const double ec = 0.5 * (e0 + e1);
+  out->n_e_max = nmax;
+  out->n_e_center = nc;
+  out->mean_energy_center_ev = ec;
+  out->omega_pe_dt = std::sqrt(nmax * kQe * kQe / (kEps0 * kMe)) * h->dt;
+  const double te = (2.0 / 3.0) * ec;  // eV
+  out->lambda_d_m = nc > 0.0 ? std::sqrt(kEps0 * te / (kQe * nc)) : 0.0;
+  out->dx_over_lambda_d = out->lambda_d_m > 0.0 ? h->dx / out->lambda_d_m : 0.0;
+  out->n_d = nc * h->p.area_m2 * out->lambda_d_m / h->p.weight;
   return latched(h);
 }
 

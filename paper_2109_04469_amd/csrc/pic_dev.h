@@ -55,6 +55,11 @@ struct DevCtl {
   int64_t pool_n[2];  // velocity-pool entries in use (live + orphaned + new)
   int64_t pbase[2];   // first pool entry of the last pass's births, per pool
   unsigned long long counters[NCOUNTERS];
+  // electrode diagnostics while measuring, [species][wall] (wall 0: x = 0)
+  unsigned long long wall_hits[2][2];      // arrivals (reflected electrons included)
+  unsigned long long wall_absorbed[2][2];  // of which absorbed
+  double wall_esum[2][2];                  // sum of impact energies, eV
+  unsigned long long ioniz_meas;           // ionizations
   uint32_t err;
   uint32_t pad;
 };

@@ -74,6 +74,10 @@ struct PartArgs {
   uint8_t* codes;
   double* acc_ew;                // CIC-weighted energy (electrons, measuring)
   unsigned long long* eepf;     // EEPF histogram (electrons, measuring)
+  unsigned long long* fedf;     // this species' arrivals per energy bin, [wall][nbins]
+  double ek_s;                  // m_s / (2 e): eV per (m/s)^2, this species
+  double fedf_inv_de;           // energy bins per eV of the arrival histogram
+  int measure_walls;            // accumulate electrode arrivals (measuring)
   int64_t cap;                  // capacity of the output arrays
   int64_t bcap;                 // capacity of the birth target arrays
   int64_t pcap;                 // capacity of this species' pool
@@ -251,6 +255,8 @@ struct pic_handle {
   double* acc_w;
   double* acc_ew;
   unsigned long long* eepf;
+  unsigned long long* fedf[2];  // [species]: [wall][eepf_bins] arrivals per energy bin
+  double fedf_emax[2];          // upper edge of the arrival energy bins, eV
   uint32_t* sort_cnt;
   uint32_t* sort_seg;
   int sort_blocks;

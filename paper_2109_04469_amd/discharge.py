@@ -174,6 +174,32 @@ class Discharge:
         check(self.L.pic_moments(self.h, ctypes.byref(out), 1 if reset else 0), "pic_moments")
         return dict(n_e=ne, n_i=ni, mean_energy_e=em, eepf=ep, steps=int(out.steps_averaged))
 
+    def wall_moments(self):
+        """Electrode fluxes, impact energies and flux-energy distributions
+        over the measured steps (libpic pic_wall_moments)."""
+        nb = int(self.params["eepf_bins"])
+        out = capi.PicWallOut()
+        f = np.zeros((2, 2, nb))
+        for k in range(2):
+            for w in range(2):
+                out.fedf[k][w] = f[k, w].ctypes.data_as(capi._DP)
+        check(self.L.pic_wall_moments(self.h, ctypes.byref(out)), "pic_wall_moments")
+        a = lambda v: np.array([[v[k][w] for w in range(2)] for k in range(2)])  # noqa: E731
+        return dict(arrivals=a(out.arrivals), absorbed=a(out.absorbed), flux=a(out.flux),
+                    absorbed_flux=a(out.absorbed_flux), mean_energy_ev=a(out.mean_energy_ev), fedf=f,
+                    fedf_emax_ev=np.array(list(out.fedf_emax_ev)), ionizations=int(out.ionizations),
+                    ionization_rate=float(out.ionization_rate), steps=int(out.steps_averaged))
+
+    def monitors(self):
+        """omega_pe dt, P_coll, Debye length, dx / lambda_D and N_D from the
+        time averages (libpic pic_get_monitors)."""
+        out = capi.PicMonitors()
+        check(self.L.pic_get_monitors(self.h, ctypes.byref(out)), "pic_get_monitors")
+        return dict(omega_pe_dt=out.omega_pe_dt, p_coll=tuple(out.p_coll), n_e_max=out.n_e_max,
+                    n_e_center=out.n_e_center, mean_energy_center_ev=out.mean_energy_center_ev,
+                    lambda_d_m=out.lambda_d_m, dx_over_lambda_d=out.dx_over_lambda_d, n_d=out.n_d,
+                    steps=int(out.steps_averaged))
+
     def counters(self):
         c = np.zeros(capi.NCOUNTERS, np.int64)
         check(self.L.pic_get_counters(self.h, _ptr(c)), "pic_get_counters")

@@ -483,3 +483,49 @@ def test_batched_launches_equal_single_runs():
     ds[2].step(3)
     assert ds[2].sync() == 0
     b.close()
+
+
+def test_electrode_diagnostics_match_oracle():
+    # Sec. 3.3 diagnostics over 40 measured steps of an evolving discharge
+    # with reflection, emission and collisions: arrivals, absorptions and
+    # ionizations are decisions (equal), the impact-energy sums FP64 (to
+    # rounding), the flux-energy histograms integers (equal).
+    import oracle
+
+    w = workloads.scaled(workloads.get("c1_small"), 8000)
+    p = dict(w["params"], flags=THOMAS, reflection=0.3, gamma_see=0.2, ion_subcycle=1,
+             rf_voltage_v=150.0)
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w, seed=13)
+    gpu, ora = pair(p, xs, init)
+    gpu.step(30)
+    assert ora.step(30) == 0
+    gpu.measure(True)
+    ora.measure(True)
+    n0 = (gpu.count(1), ora.count(1))
+    gpu.step(40)
+    assert ora.step(40) == 0
+    wg = gpu.wall_moments()
+    wo = ora.wall_moments()
+    r = wo["raw"]
+    assert wg["steps"] == r["steps"] == 40
+    assert np.array_equal(wg["arrivals"], r["hits"]) and r["hits"].sum() > 0
+    assert np.array_equal(wg["absorbed"], r["absorbed"])
+    assert wg["ionizations"] == r["ionizations"]
+    np.testing.assert_allclose(wg["mean_energy_ev"], wo["mean_energy_ev"], rtol=1e-9)
+    np.testing.assert_allclose(wg["flux"], wo["flux"], rtol=1e-14)
+    assert wg["ionization_rate"] == pytest.approx(wo["ionization_rate"], rel=1e-14)
+    np.testing.assert_allclose(wg["fedf_emax_ev"], r["emax"], rtol=0)
+    assert np.array_equal(wg["fedf"], wo["fedf"])
+    # the ion balance holds exactly on the GPU as well
+    assert gpu.count(1) - n0[0] == wg["ionizations"] - wg["absorbed"][1].sum()
+    # monitors from the time averages
+    mg = gpu.monitors()
+    mo = oracle.monitors(ora.moments(), p, (gpu.derived()["p_coll_e"], gpu.derived()["p_coll_i"]))
+    for k in ("omega_pe_dt", "n_e_max", "n_e_center", "mean_energy_center_ev", "lambda_d_m",
+              "dx_over_lambda_d", "n_d"):
+        assert mg[k] == pytest.approx(mo[k], rel=1e-9), k
+    assert mg["p_coll"] == pytest.approx(mo["p_coll"], rel=1e-15)
+    # a moments reset clears the electrode diagnostics too
+    gpu.moments(reset=True)
+    assert gpu.wall_moments()["arrivals"].sum() == 0
