@@ -196,7 +196,9 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
         c |= 1u;
       }
     }
-    if (a.measure_walls) record_arrival<SP>(a, slot, vx_hit, wall, !alive);
+    // electrons record arrivals only in the measuring variant (the same
+    // condition: it runs exactly when measuring), ions by the runtime flag
+    if (SP == 0 ? MEASURE : (a.measure_walls != 0)) record_arrival<SP>(a, slot, vx_hit, wall, !alive);
   }
   if (alive && cand) {
     if (SP == 0) {
@@ -221,7 +223,7 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
         b = 1;
         mul = 2;
         atomicAdd(&s_cnt[C_E_ION], 1ull);
-        if (a.measure_walls) atomicAdd(&a.ctl->ioniz_meas, 1ull);
+        if (MEASURE) atomicAdd(&a.ctl->ioniz_meas, 1ull);
         deposit_global(a.dep_other, x, a.inv_dx, a.nx);
       }
       c |= proc << 3;
