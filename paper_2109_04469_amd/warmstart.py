@@ -164,6 +164,42 @@ def generate(n_train=96, n_test=16, cycles=2000, avg_windows=20, seed=0):
     }
 
 
+def run_to_convergence(ds, steps_per_cycle, delta=0.01, block_windows=10, max_cycles=5000,
+                       on_block=None):
+    """Advances discharges (one batch) until each is steady: its ion density
+    profile averaged over the last block of `block_windows` windows of
+    WINDOW_CYCLES cycles differs from the previous block's by at most delta
+    (relative L2). A discharge that is steady leaves the batch; returns the
+    RF cycles each needed (None if max_cycles passed first) and the last
+    block averages {n_e, n_i, mean_energy_e, eepf} of each."""
+    n = len(ds)
+    done = [None] * n
+    last = [None] * n
+    prev = [None] * n
+    active = list(range(n))
+    cycles = 0
+    block = block_windows * WINDOW_CYCLES
+    while active and cycles < max_cycles:
+        win, _, failed = run_windows([ds[i] for i in active], block, steps_per_cycle)
+        cycles += block
+        avg = final_average(win, block_windows)
+        still = []
+        for k, i in enumerate(active):
+            if failed[k]:
+                continue  # dropped: never steady
+            cur = {key: v[k] for key, v in avg.items()}
+            if prev[i] is not None and rel_l2(cur["n_i"], prev[i]["n_i"]) <= delta:
+                done[i] = cycles
+            else:
+                still.append(i)
+            prev[i] = cur
+            last[i] = cur
+        active = still
+        if on_block:
+            on_block(cycles, len(active))
+    return done, last
+
+
 # ---- the network -----------------------------------------------------------------
 
 class Surrogate:

@@ -106,3 +106,42 @@ def constant(n, dv_e, dv_i, sig_e=(1e-19, 0.0, 0.0), sig_i=(1e-18, 0.0),
         [np.full(n, float(s)) for s in sig_i],
         exc_threshold_ev, ion_threshold_ev,
     )
+
+
+def read_two_column(path):
+    """A cross section as two whitespace-separated columns, energy in eV and
+    sigma in m^2 (lines starting with '#' skipped), as tabulated data sets
+    (e.g. from LXCat) are commonly exported."""
+    a = np.loadtxt(path, comments="#", dtype=np.float64, ndmin=2)
+    e, s = a[:, 0], a[:, 1]
+    if not np.all(np.diff(e) > 0):
+        raise ValueError(f"{path}: energies must increase")
+    return e, s
+
+
+def from_energy_tables(electron, ion, n=8192, emax_e_ev=3000.0, emax_i_ev=3000.0,
+                       exc_threshold_ev=EXC_THRESHOLD_EV, ion_threshold_ev=ION_THRESHOLD_EV):
+    """Tables in the library's layout from cross sections given on energy
+    grids: electron = [(eV, m^2) for elastic, excitation, ionization], ion =
+    [(eV, m^2) for isotropic, backward] (ion energies in the lab frame of
+    1/2 M g^2). Each is interpolated linearly in energy at the table speeds;
+    inelastic processes are zero below their thresholds, and beyond its last
+    energy a table keeps its last value."""
+    vmax_e = np.sqrt(2.0 * emax_e_ev * E_CHARGE / M_ELECTRON)
+    vmax_i = np.sqrt(2.0 * emax_i_ev * E_CHARGE / M_ARGON)
+    dv_e = vmax_e / (n - 1)
+    dv_i = vmax_i / (n - 1)
+    k = np.arange(n, dtype=np.float64)
+    eps_e = 0.5 * M_ELECTRON * (k * dv_e) ** 2 / E_CHARGE
+    eps_i = 0.5 * M_ARGON * (k * dv_i) ** 2 / E_CHARGE
+    if len(electron) != 3 or len(ion) != 2:
+        raise ValueError("need three electron and two ion processes")
+    se = []
+    for p, (e, s) in enumerate(electron):
+        t = np.interp(eps_e, e, s)
+        thr = (None, exc_threshold_ev, ion_threshold_ev)[p]
+        if thr is not None:
+            t[eps_e < thr] = 0.0
+        se.append(np.maximum(t, 0.0))
+    si = [np.maximum(np.interp(eps_i, e, s), 0.0) for e, s in ion]
+    return XsecTables(n, dv_e, dv_i, se, si, exc_threshold_ev, ion_threshold_ev)

@@ -166,3 +166,23 @@ def test_warm_start_pipeline_small():
     assert res["n_test"] == 2 and all(res["warm_loaded"])
     assert len(res["initial_rel_l2_n_i"]["warm"]) == 2
     assert res["train_loss"][-1][1] < res["train_loss"][0][1]
+
+
+def test_run_to_convergence_driver():
+    # steady-state driver: discharges leave the batch once their block
+    # averages stop changing; a loose tolerance ends a short run
+    from paper_2109_04469_amd import Discharge, warmstart
+    from pic_inputs import warm, xsec
+
+    ws = warm.draw(3, seed=4)
+    xs = xsec.argon_synthetic()
+    import torch
+
+    s = torch.cuda.Stream()
+    ds = [Discharge(w["params"], xs, stream=s) for w in ws]
+    for k, (d, w) in enumerate(zip(ds, ws)):
+        warmstart.start_cold(d, w, seed=k)
+    done, last = warmstart.run_to_convergence(ds, warm.STEPS_PER_CYCLE, delta=0.5, block_windows=1,
+                                              max_cycles=60)
+    assert all(c is not None and c <= 60 for c in done)
+    assert all(np.all(np.isfinite(m["n_i"])) for m in last)
