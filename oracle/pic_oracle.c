@@ -48,6 +48,9 @@ void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 #define F_NO_COLL 4u
 #define F_IMMOBILE_IONS 8u
 #define F_RECORD 16u
+#define F_ANISO 64u /* screened-Coulomb electron elastic scattering (variant) */
+#define F_OPAL 128u /* Opal et al. ionization energy sharing (variant) */
+#define OPAL_W 10.0 /* eV, argon */
 
 enum { C_STEPS = 0, C_E_PUSHED, C_I_PUSHED, C_E_ABSORBED, C_E_REFLECTED, C_I_ABSORBED,
        C_SE_EMITTED, C_E_CAND, C_E_ELASTIC, C_E_EXC, C_E_ION, C_I_CAND, C_I_ISO, C_I_BACK,
@@ -141,6 +144,43 @@ static void iso_dir(double ua, double ub, double* nx, double* ny, double* nz) {
   *nx = cth;
   *ny = sth * cos(ph);
   *nz = sth * sin(ph);
+}
+
+/* Variant of the electron elastic scattering direction (Vahedi & Surendra,
+ * 1995): deflection chi from the incident direction e (unit vector) with
+ * cos chi = (2 + eps - 2 (1 + eps)^u) / eps for energy eps in eV (uniform
+ * in (-1, 1) at eps = 0), azimuth phi = 2 pi w measured in the plane normal
+ * to e from b1 = unit(e x a) towards b2 = e x b1, where a is the x axis, or
+ * the y axis when |e_x| >= 0.9. */
+static void deflect(double ex, double ey, double ez, double eps, double u, double w, double* nx,
+                    double* ny, double* nz) {
+  double c;
+  if (eps > 0.0)
+    c = (2.0 + eps - 2.0 * pow(1.0 + eps, u)) / eps;
+  else
+    c = 1.0 - 2.0 * u;
+  if (c > 1.0) c = 1.0;
+  if (c < -1.0) c = -1.0;
+  double s2 = 1.0 - c * c;
+  double sn = sqrt(s2 > 0.0 ? s2 : 0.0);
+  double ph = TWO_PI * w;
+  double b1[3];
+  if (fabs(ex) < 0.9) {
+    double r = sqrt(ey * ey + ez * ez);
+    b1[0] = 0.0;
+    b1[1] = ez / r;
+    b1[2] = -ey / r;
+  } else {
+    double r = sqrt(ez * ez + ex * ex);
+    b1[0] = -ez / r;
+    b1[1] = 0.0;
+    b1[2] = ex / r;
+  }
+  double b2[3] = {ey * b1[2] - ez * b1[1], ez * b1[0] - ex * b1[2], ex * b1[1] - ey * b1[0]};
+  double cp = cos(ph), sp = sin(ph);
+  *nx = c * ex + sn * (cp * b1[0] + sp * b2[0]);
+  *ny = c * ey + sn * (cp * b1[1] + sp * b2[1]);
+  *nz = c * ez + sn * (cp * b1[2] + sp * b2[2]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -706,7 +746,11 @@ int ora_step(ora_sim* s, int64_t nsteps) {
                  * the centre-of-mass frame */
                 draw(s, i, 0, 1, r1);
                 double nx_, ny_, nz_;
-                iso_dir(u01(r1[0]), u01(r1[1]), &nx_, &ny_, &nz_);
+                if ((p->flags & F_ANISO) && speed > 0.0)
+                  deflect(vx / speed, vy / speed, vz / speed, s->ek_e * v2, u01(r1[0]), u01(r1[1]),
+                          &nx_, &ny_, &nz_);
+                else
+                  iso_dir(u01(r1[0]), u01(r1[1]), &nx_, &ny_, &nz_);
                 double g = s->mm_e * speed;
                 vx = s->mr_e * vx + g * nx_;
                 vy = s->mr_e * vy + g * ny_;
@@ -736,7 +780,11 @@ int ora_step(ora_sim* s, int64_t nsteps) {
                 draw(s, i, 0, 3, r3);
                 double eps = s->ek_e * v2 - p->ion_threshold_ev;
                 if (eps < 0.0) eps = 0.0;
-                double e_ej = u01(r2[0]) * eps;
+                /* uniform sharing, or (variant) the Opal et al. form whose
+                 * cumulative distribution on [0, eps/2] is
+                 * atan(e / w) / atan(eps / (2 w)) */
+                double e_ej = (p->flags & F_OPAL) ? OPAL_W * tan(u01(r2[0]) * atan(eps / (2.0 * OPAL_W)))
+                                                  : u01(r2[0]) * eps;
                 double e_sc = eps - e_ej;
                 double s_sc = sqrt(e_sc * s->ve_e);
                 double s_ej = sqrt(e_ej * s->ve_e);

@@ -12,6 +12,7 @@ EPS0 = 8.8541878128e-12
 KB = 1.380649e-23
 
 NO_FIELD, FIXED_E, NO_COLL, IMMOBILE_IONS, RECORD, THOMAS = 1, 2, 4, 8, 16, 32
+ANISO, OPAL = 64, 128
 
 
 def params(base="c1_small", **over):
