@@ -59,6 +59,16 @@ extern "C" {
 #define PIC_FLAG_THOMAS         (1u << 5) /* solve Poisson with the serial Thomas
                                              recurrence instead of the exact
                                              integer prefix-sum form           */
+/* method variants (not in the paper, whose scattering is isotropic and whose
+ * ionization shares the energy uniformly): */
+#define PIC_FLAG_ANISO_ELASTIC  (1u << 6) /* electron elastic scattering with the
+   screened-Coulomb angular distribution of Vahedi & Surendra (1995):
+   cos chi = (2 + eps - 2 (1 + eps)^u) / eps, eps the electron energy in eV,
+   about the incident direction, azimuth uniform, in the two-body frame   */
+#define PIC_FLAG_OPAL_SHARING   (1u << 7) /* ionization energy shared as in Opal,
+   Peterson & Beaty (1971): the ejected electron takes
+   eps_ej = w tan(u atan(eps' / (2 w))), w = 10 eV (argon), eps' the energy
+   above threshold; the scattered one the rest                            */
 
 /* ---- event counters (pic_get_counters), accumulated since pic_set_state --- */
 enum {

@@ -743,6 +743,39 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
 // in this pass, at slot bbase + r of the other species with pool entries
 // pbase + r. E is read from global memory here (the same values k_decide
 // used).
+// Direction after a deflection by chi from the incident unit vector e, with
+// cos chi = (2 + eps - 2 (1 + eps)^u) / eps (eps in eV; uniform cos chi when
+// eps = 0) and azimuth 2 pi w, about e: n = cos chi e + sin chi (cos phi b1 +
+// sin phi b2), b1 the unit vector along e x (1, 0, 0) (e x (0, 1, 0) when e
+// is within 26 degrees of the x axis), b2 = e x b1.
+__device__ __forceinline__ void aniso_dir(double ex, double ey, double ez, double eps, double u,
+                                          double w, double& nx, double& ny, double& nz) {
+  double c = eps > 0.0 ? (2.0 + eps - 2.0 * pow(1.0 + eps, u)) / eps : 1.0 - 2.0 * u;
+  c = fmin(fmax(c, -1.0), 1.0);
+  const double sn = sqrt(fmax(1.0 - c * c, 0.0));
+  const double ph = kTwoPi * w;
+  double sp, cp;
+  sincos(ph, &sp, &cp);
+  double b1x, b1y, b1z;
+  if (fabs(ex) < 0.9) {  // e x (1, 0, 0) = (0, ez, -ey)
+    const double r = sqrt(ey * ey + ez * ez);
+    b1x = 0.0;
+    b1y = ez / r;
+    b1z = -ey / r;
+  } else {  // e x (0, 1, 0) = (-ez, 0, ex)
+    const double r = sqrt(ez * ez + ex * ex);
+    b1x = -ez / r;
+    b1y = 0.0;
+    b1z = ex / r;
+  }
+  const double b2x = ey * b1z - ez * b1y;
+  const double b2y = ez * b1x - ex * b1z;
+  const double b2z = ex * b1y - ey * b1x;
+  nx = c * ex + sn * (cp * b1x + sp * b2x);
+  ny = c * ey + sn * (cp * b1y + sp * b2y);
+  nz = c * ez + sn * (cp * b1z + sp * b2z);
+}
+
 template <int SP>
 __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long* s_cnt,
                                           int64_t slot, uint32_t c, int64_t dest, int64_t r,
@@ -761,10 +794,15 @@ __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long*
     const uint4 r1 = draw(step, (uint32_t)slot, 0, 1, a.seed, a.run);
     const double v2 = vx * vx + vy * vy + vz * vz;
     if (proc == 2) {
-      // elastic on an atom at rest, isotropic in the CM frame
+      // elastic on an atom at rest: isotropic in the CM frame, or (variant)
+      // deflected by the screened-Coulomb angle about the incident direction
       const double speed = sqrt(v2);
       double nx_, ny_, nz_;
-      iso_dir(u01(r1.x), u01(r1.y), nx_, ny_, nz_);
+      if ((a.model & kModelAniso) && speed > 0.0)
+        aniso_dir(vx / speed, vy / speed, vz / speed, a.ek * v2, u01(r1.x), u01(r1.y), nx_, ny_,
+                  nz_);
+      else
+        iso_dir(u01(r1.x), u01(r1.y), nx_, ny_, nz_);
       const double gg = a.mm * speed;
       vx = a.mr * vx + gg * nx_;
       vy = a.mr * vy + gg * ny_;
@@ -786,7 +824,10 @@ __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long*
       const uint4 r3 = draw(step, (uint32_t)slot, 0, 3, a.seed, a.run);
       double eps = a.ek * v2 - a.ion_thr;
       if (eps < 0.0) eps = 0.0;
-      const double e_ej = u01(r2.x) * eps;
+      // energy above threshold shared uniformly, or (variant) as Opal et al.
+      const double e_ej = (a.model & kModelOpal)
+                              ? kOpalW * tan(u01(r2.x) * atan(eps / (2.0 * kOpalW)))
+                              : u01(r2.x) * eps;
       const double e_sc = eps - e_ej;
       const double s_sc = sqrt(e_sc * a.ve);
       const double s_ej = sqrt(e_ej * a.ve);

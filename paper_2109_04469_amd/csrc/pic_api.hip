@@ -74,7 +74,8 @@ int validate(const pic_params* p, const pic_xsec* xs) {
     if (!xs->sigma_i[k]) return PIC_EINVAL;
   if (!(xs->exc_threshold_ev >= 0) || !(xs->ion_threshold_ev >= 0)) return PIC_EINVAL;
   const uint32_t known = PIC_FLAG_NO_FIELD | PIC_FLAG_FIXED_E | PIC_FLAG_NO_COLL |
-                         PIC_FLAG_IMMOBILE_IONS | PIC_FLAG_RECORD | PIC_FLAG_THOMAS;
+                         PIC_FLAG_IMMOBILE_IONS | PIC_FLAG_RECORD | PIC_FLAG_THOMAS |
+                         PIC_FLAG_ANISO_ELASTIC | PIC_FLAG_OPAL_SHARING;
   if (p->flags & ~known) return PIC_EINVAL;
   return PIC_OK;
 }
@@ -276,6 +277,8 @@ PartArgs particle_args(pic_handle* h, int sp, int parity) {
   a.run = h->p.run;
   a.no_coll = (h->p.flags & PIC_FLAG_NO_COLL) ? 1 : 0;
   a.record = (h->p.flags & PIC_FLAG_RECORD) ? 1 : 0;
+  a.model = ((h->p.flags & PIC_FLAG_ANISO_ELASTIC) ? kModelAniso : 0) |
+            ((h->p.flags & PIC_FLAG_OPAL_SHARING) ? kModelOpal : 0);
   return a;
 }
 

@@ -112,7 +112,11 @@ struct PartArgs {
   uint32_t run;
   int no_coll;
   int record;
+  int model;  // kModelAniso | kModelOpal
 };
+constexpr int kModelAniso = 1;  // anisotropic electron elastic scattering
+constexpr int kModelOpal = 2;   // Opal energy sharing in ionization
+constexpr double kOpalW = 10.0;  // eV, argon
 
 struct SortArgs {
   const double* sx;  // input: x, v_x, pool index, pool
