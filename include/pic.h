@@ -341,6 +341,20 @@ int pic_batch_step(pic_batch* b, int64_t n_steps);
 /* Synchronises the batch's stream and releases its host memory. */
 void pic_batch_free(pic_batch* b);
 
+/* Launch shape of the particle kernels: decide_wg_per_cu and
+ * emit_wg_per_cu workgroups per compute unit for the decide and emit
+ * kernels of both species (clamped to [1, what fits on a CU] and to the tile
+ * count; the default is the most that fits). Results do not depend on it:
+ * the tiles and every per-slot decision are the same for any grid. */
+int pic_set_launch(pic_handle* h, int decide_wg_per_cu, int emit_wg_per_cu);
+
+/* Picks the launch shape by measurement: advances the discharge by
+ * steps_per_trial steps per candidate (every decide shape, then every emit
+ * shape), timing the electron decide and emit kernels with events, and keeps
+ * the fastest; the chosen shape is returned through the pointers (may be
+ * NULL). The steps are ordinary steps of the discharge. Synchronises. */
+int pic_tune(pic_handle* h, int64_t steps_per_trial, int* decide_wg_per_cu, int* emit_wg_per_cu);
+
 /* Kernel timing with HIP events recorded on the handle's stream
  * (measurement surface). level 0: off. level 1: two event records around
  * the field kernel, each species' particle pass (PIC_TIMER_ELECTRON,

@@ -1216,13 +1216,25 @@ PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, in
     else
       bpc = blocks_per_cu(k_decide<1, false>, c.lds_decide[m], kDB);
     c.grid_decide[m] = clamp_grid((int64_t)bpc * num_cu, max_tiles);
+    c.bpc_decide[m] = bpc;
   }
   c.lds_emit = emit_lds(nx);
   const int bpc = species == 0 ? blocks_per_cu(k_emit<0>, c.lds_emit)
                                : blocks_per_cu(k_emit<1>, c.lds_emit);
   c.grid_emit = clamp_grid((int64_t)bpc * num_cu, max_tiles);
+  c.bpc_emit = bpc;
   c.grid_rare = num_cu * 2;
+  c.max_tiles = max_tiles;
   return c;
+}
+
+void particle_launch_set(PartLaunch& c, int num_cu, int kd, int ke) {
+  for (int m = 0; m < 2; ++m) {
+    const int k = kd < 1 ? 1 : (kd > c.bpc_decide[m] ? c.bpc_decide[m] : kd);
+    c.grid_decide[m] = clamp_grid((int64_t)k * num_cu, c.max_tiles);
+  }
+  const int k = ke < 1 ? 1 : (ke > c.bpc_emit ? c.bpc_emit : ke);
+  c.grid_emit = clamp_grid((int64_t)k * num_cu, c.max_tiles);
 }
 
 hipError_t launch_particle_kernel(int kernel, int species, bool measure, const PartArgs& a,

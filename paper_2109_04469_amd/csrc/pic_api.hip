@@ -1250,6 +1250,64 @@ int pic_get_decisions(pic_handle* h, int species, uint8_t* codes, int64_t cap, i
   return latched(h);
 }
 
+int pic_set_launch(pic_handle* h, int decide_wg_per_cu, int emit_wg_per_cu) {
+  if (!h || decide_wg_per_cu < 1 || emit_wg_per_cu < 1) return PIC_EINVAL;
+  for (int s = 0; s < 2; ++s) particle_launch_set(h->launch[s], h->num_cu, decide_wg_per_cu, emit_wg_per_cu);
+  return PIC_OK;
+}
+
+int pic_tune(pic_handle* h, int64_t steps_per_trial, int* decide_wg_per_cu, int* emit_wg_per_cu) {
+  if (!h || steps_per_trial < 1) return PIC_EINVAL;
+  // time one kernel of the electron pass over steps_per_trial steps with
+  // events around every particle kernel, without disturbing the caller's
+  // accumulated timers
+  const int level = h->timing;
+  auto trial = [&](int timer, double* us) -> int {
+    int st = timer_collect(h);
+    if (st) return st;
+    const double ms0 = h->t_ms[timer];
+    const int64_t n0 = h->t_n[timer];
+    h->timing = 2;
+    st = pic_step(h, steps_per_trial);
+    if (!st) st = timer_collect(h);
+    h->timing = level;
+    if (st) return st;
+    const int64_t n = h->t_n[timer] - n0;
+    *us = n ? 1e3 * (h->t_ms[timer] - ms0) / (double)n : 0.0;
+    h->t_ms[timer] = ms0;
+    h->t_n[timer] = n0;
+    return PIC_OK;
+  };
+  const PartLaunch& c = h->launch[0];
+  int kd = c.bpc_decide[0], ke = c.bpc_emit;
+  double best = -1.0;
+  for (int k = 1; k <= c.bpc_decide[0]; ++k) {
+    pic_set_launch(h, k, ke);
+    double us = 0.0;
+    const int st = trial(PIC_TIMER_E_DECIDE, &us);
+    if (st) return st;
+    if (best < 0.0 || us < best) {
+      best = us;
+      kd = k;
+    }
+  }
+  best = -1.0;
+  for (int k = 1; k <= c.bpc_emit; ++k) {
+    pic_set_launch(h, kd, k);
+    double us = 0.0;
+    const int st = trial(PIC_TIMER_E_EMIT, &us);
+    if (st) return st;
+    if (best < 0.0 || us < best) {
+      best = us;
+      ke = k;
+    }
+  }
+  pic_set_launch(h, kd, ke);
+  if (decide_wg_per_cu) *decide_wg_per_cu = kd;
+  if (emit_wg_per_cu) *emit_wg_per_cu = ke;
+  return latched(h);
+}
+
 int pic_timing(pic_handle* h, int level) {
   if (!h || level < 0 || level > 2) return PIC_EINVAL;
   h->timing = level;

@@ -148,8 +148,14 @@ struct PartLaunch {
   int grid_emit;
   size_t lds_emit;
   int grid_rare;
+  int bpc_decide[2];   // resident workgroups per CU at these LDS sizes (occupancy)
+  int bpc_emit;
+  int64_t max_tiles;
 };
 PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, int64_t max_tiles);
+// the same with k_decide at kd and k_emit at ke workgroups per CU (clamped
+// to [1, occupancy] and to the tile count)
+void particle_launch_set(PartLaunch& c, int num_cu, int kd, int ke);
 // kernel 0: k_decide, 1: k_emit, 2: k_rare (launched in this order)
 hipError_t launch_particle_kernel(int kernel, int species, bool measure, const PartArgs& a,
                                   const PartLaunch& c, hipStream_t s);

@@ -212,6 +212,19 @@ class Discharge:
         check(self.L.pic_get_decisions(self.h, species, _ptr(buf), cap, ctypes.byref(n)), "pic_get_decisions")
         return buf[: n.value].copy()
 
+    def set_launch(self, decide_wg_per_cu, emit_wg_per_cu):
+        check(self.L.pic_set_launch(self.h, int(decide_wg_per_cu), int(emit_wg_per_cu)),
+              "pic_set_launch")
+
+    def tune(self, steps_per_trial=100):
+        """Measures the particle kernels' launch shapes on this discharge
+        (advancing it) and keeps the fastest; returns (decide, emit)
+        workgroups per CU."""
+        kd, ke = ctypes.c_int(), ctypes.c_int()
+        check(self.L.pic_tune(self.h, int(steps_per_trial), ctypes.byref(kd), ctypes.byref(ke)),
+              "pic_tune")
+        return kd.value, ke.value
+
     def timing(self, level=1):
         """0: off; 1: events around the field kernel, each species' particle
         pass and each sort; 2: also around every single particle kernel."""

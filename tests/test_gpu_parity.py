@@ -559,3 +559,28 @@ def test_method_variants_single_step_match_oracle():
             assert np.sum(((dg >> 3) & 7) == 2) > 100 and np.sum(((dg >> 3) & 7) == 4) > 20
         assert_state_close(gpu.get_state(sp), ora.get_state(sp), L, vs, rtol=1e-10, what=f"species {sp}")
     assert np.array_equal(gpu.counters(), ora.counters())
+
+
+def test_launch_shape_does_not_change_results():
+    # grid sizes change which workgroup takes which tile, never a result
+    from paper_2109_04469_amd import Discharge
+
+    w = workloads.scaled(workloads.get("c1_small"), 9000)
+    p = dict(w["params"], reflection=0.3, gamma_see=0.2, sort_interval=20)
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w, seed=21)
+    ds = []
+    for shape in ((1, 1), (3, 4), (2, 3)):
+        d = Discharge(p, xs)
+        for sp in (0, 1):
+            d.set_state(sp, *init[sp], step=0)
+        d.set_launch(*shape)
+        d.step(60)
+        assert d.sync() == 0
+        ds.append(d)
+    for d in ds[1:]:
+        for sp in (0, 1):
+            assert_state_equal(d.get_state(sp), ds[0].get_state(sp), what=f"species {sp}")
+        assert np.array_equal(d.counters(), ds[0].counters())
+    kd, ke = ds[0].tune(10)
+    assert kd >= 1 and ke >= 1 and ds[0].sync() == 0
