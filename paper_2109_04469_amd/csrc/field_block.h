@@ -76,14 +76,12 @@ __device__ __forceinline__ int64_t block_excl_scan64(int64_t v, int64_t& excl, i
   const int64_t inc = wave_incl_scan<long long>((long long)v);
   if (lane == kWave - 1) s_wave[wave] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int w = 0; w < kFieldWaves; ++w) {
-      int64_t t = s_wave[w];
-      s_wave[w] = run;
-      run += t;
-    }
-    s_wave[kFieldWaves] = run;
+  if (wave == 0) {
+    // exclusive scan of the wave totals by the first wave
+    const int64_t t = lane < kFieldWaves ? s_wave[lane] : 0;
+    const int64_t ti = wave_incl_scan<long long>((long long)t);
+    if (lane < kFieldWaves) s_wave[lane] = ti - t;
+    if (lane == kFieldWaves - 1) s_wave[kFieldWaves] = ti;
   }
   __syncthreads();
   excl = s_wave[wave] + inc - v;
@@ -98,14 +96,15 @@ __device__ __forceinline__ i128p block_excl_scan128(i128p v, i128p& excl, i128p*
   const i128p inc = wave_incl_scan128(v);
   if (lane == kWave - 1) s_wave[wave] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    i128p run = from64(0);
-    for (int w = 0; w < kFieldWaves; ++w) {
-      i128p t = s_wave[w];
-      s_wave[w] = run;
-      run = add128(run, t);
-    }
-    s_wave[kFieldWaves] = run;
+  if (wave == 0) {
+    // exclusive scan of the wave totals by the first wave
+    const i128p t = lane < kFieldWaves ? s_wave[lane] : from64(0);
+    const i128p ti = wave_incl_scan128(t);
+    i128p neg_t;
+    neg_t.lo = ~t.lo + 1;
+    neg_t.hi = ~t.hi + (neg_t.lo == 0 ? 1 : 0);
+    if (lane < kFieldWaves) s_wave[lane] = add128(ti, neg_t);
+    if (lane == kFieldWaves - 1) s_wave[kFieldWaves] = ti;
   }
   __syncthreads();
   // excl = s_wave[wave] + inc - v

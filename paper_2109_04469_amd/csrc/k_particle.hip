@@ -776,7 +776,9 @@ __device__ __forceinline__ void aniso_dir(double ex, double ey, double ez, doubl
   nz = c * ez + sn * (cp * b1z + sp * b2z);
 }
 
-template <int SP>
+// VAR: the method-variant paths (anisotropic elastic scattering, Opal
+// sharing) are compiled in; without them the kernels stay smaller.
+template <int SP, bool VAR>
 __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long* s_cnt,
                                           int64_t slot, uint32_t c, int64_t dest, int64_t r,
                                           int64_t bbase) {
@@ -798,7 +800,7 @@ __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long*
       // deflected by the screened-Coulomb angle about the incident direction
       const double speed = sqrt(v2);
       double nx_, ny_, nz_;
-      if ((a.model & kModelAniso) && speed > 0.0)
+      if (VAR && (a.model & kModelAniso) && speed > 0.0)
         aniso_dir(vx / speed, vy / speed, vz / speed, a.ek * v2, u01(r1.x), u01(r1.y), nx_, ny_,
                   nz_);
       else
@@ -825,7 +827,7 @@ __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long*
       double eps = a.ek * v2 - a.ion_thr;
       if (eps < 0.0) eps = 0.0;
       // energy above threshold shared uniformly, or (variant) as Opal et al.
-      const double e_ej = (a.model & kModelOpal)
+      const double e_ej = (VAR && (a.model & kModelOpal))
                               ? kOpalW * tan(u01(r2.x) * atan(eps / (2.0 * kOpalW)))
                               : u01(r2.x) * eps;
       const double e_sc = eps - e_ej;
@@ -920,7 +922,7 @@ __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long*
   }
 }
 
-template <int SP>
+template <int SP, bool VAR>
 __global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
   __shared__ unsigned long long s_cnt[NCOUNTERS];
   const int tid = threadIdx.x;
@@ -933,7 +935,7 @@ __global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
   const int64_t nb = gridDim.x;
   for (int64_t i = (int64_t)blockIdx.x + nb * tid; i < n; i += nb * kBlock) {
     const uint4 q = a.rq[i];
-    rare_slot<SP>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
+    rare_slot<SP, VAR>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
   }
   __syncthreads();
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
@@ -946,7 +948,7 @@ __global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
 // The two are independent: the field goes to the other E buffer, and the
 // queued slots read the E of this step.
 
-template <int SP>
+template <int SP, bool VAR>
 __global__ __launch_bounds__(kFieldThreads) void k_tail(FieldArgs f, PartArgs a) {
   if (blockIdx.x == 0) {
     field_block(f);
@@ -963,7 +965,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_tail(FieldArgs f, PartArgs a)
   const int64_t nb = gridDim.x - 1;
   for (int64_t i = (int64_t)(blockIdx.x - 1) + nb * tid; i < n; i += nb * kFieldThreads) {
     const uint4 q = a.rq[i];
-    rare_slot<SP>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
+    rare_slot<SP, VAR>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
   }
   __syncthreads();
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
@@ -972,10 +974,12 @@ __global__ __launch_bounds__(kFieldThreads) void k_tail(FieldArgs f, PartArgs a)
 hipError_t launch_tail(int species, const FieldArgs& f, const PartArgs& a, int rare_blocks,
                        hipStream_t s) {
   if (f.nx > kMaxNx || f.nx < 3 || rare_blocks < 1) return hipErrorInvalidValue;
-  if (species == 0)
-    hipLaunchKernelGGL((k_tail<0>), dim3(1 + rare_blocks), dim3(kFieldThreads), 0, s, f, a);
+  if (species == 0 && a.model)
+    hipLaunchKernelGGL((k_tail<0, true>), dim3(1 + rare_blocks), dim3(kFieldThreads), 0, s, f, a);
+  else if (species == 0)
+    hipLaunchKernelGGL((k_tail<0, false>), dim3(1 + rare_blocks), dim3(kFieldThreads), 0, s, f, a);
   else
-    hipLaunchKernelGGL((k_tail<1>), dim3(1 + rare_blocks), dim3(kFieldThreads), 0, s, f, a);
+    hipLaunchKernelGGL((k_tail<1, false>), dim3(1 + rare_blocks), dim3(kFieldThreads), 0, s, f, a);
   return hipGetLastError();
 }
 
@@ -1132,39 +1136,42 @@ __global__ __launch_bounds__(kBlock) void k_emit_b(const PartArgs* __restrict__ 
 }
 
 // Queued slots of n discharges laid end to end (s_rs: prefix of their
-// counts), entries i0, i0 + stride, ...
-template <int SP>
-__device__ __forceinline__ void rare_run(const PartArgs* __restrict__ args, int n,
-                                         const int64_t* s_rs, int64_t i0, int64_t stride) {
-  const int64_t R = s_rs[n];
-  for (int64_t i = i0; i < R; i += stride) {
-    // the last discharge whose run starts at or before i
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_rs[mid] <= i) lo = mid;
-      else hi = mid - 1;
+// counts): this workgroup's contiguous run of them, one discharge segment at
+// a time so that the discharge's arguments are uniform over the workgroup.
+template <int SP, int NT, bool VAR>
+__device__ __forceinline__ void rare_segments(const PartArgs* __restrict__ args, int n,
+                                              const int64_t* s_rs, int wg, int nwg) {
+  const int64_t R = uniform64(s_rs[n]);
+  const int64_t tb = uniform64(R * (int64_t)wg / (int64_t)nwg);
+  const int64_t te = uniform64(R * ((int64_t)wg + 1) / (int64_t)nwg);
+  int d = next_owner(s_rs, n, 0, tb);
+  for (int64_t t = tb; t < te;) {
+    const PartArgs& a = args[d];
+    const int64_t rs = uniform64(s_rs[d]);
+    const int64_t se = min(te, uniform64(s_rs[d + 1]));
+    const int64_t bbase = uniform64(SP == 0 ? a.ctl->n_i[a.parity] : a.ctl->e_out);
+    unsigned long long* cnt = a.ctl->counters;
+    for (int64_t i = t + threadIdx.x; i < se; i += NT) {
+      const uint4 q = a.rq[i - rs];
+      rare_slot<SP, VAR>(a, cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
     }
-    const PartArgs& a = args[lo];
-    const uint4 q = a.rq[i - s_rs[lo]];
-    const int64_t bbase = SP == 0 ? a.ctl->n_i[a.parity] : a.ctl->e_out;
-    rare_slot<SP>(a, a.ctl->counters, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
+    t = se;
+    d = next_owner(s_rs, n, d + 1, t);
   }
 }
 
-template <int SP>
+template <int SP, bool VAR>
 __global__ __launch_bounds__(kBlock) void k_rare_b(const PartArgs* __restrict__ args, int n) {
   __shared__ int64_t s_rs[kMaxBatch + 1];
   __shared__ int64_t s_w[kBlock / kWave];
   const int tid = threadIdx.x;
   block_exclusive<kBlock>(tid < n ? args[tid].ctl->n_rare[SP] : 0, n, s_rs, s_w);
-  const int64_t nb = gridDim.x;
-  rare_run<SP>(args, n, s_rs, (int64_t)blockIdx.x + nb * tid, nb * kBlock);
+  rare_segments<SP, kBlock, VAR>(args, n, s_rs, blockIdx.x, gridDim.x);
 }
 
 // Workgroups [0, nf) solve the next step's field of nf discharges; the
 // others take the queued slots of the last particle pass of n discharges.
-template <int SP>
+template <int SP, bool VAR>
 __global__ __launch_bounds__(kFieldThreads) void k_tail_b(const FieldArgs* __restrict__ f, int nf,
                                                           const PartArgs* __restrict__ args,
                                                           int n) {
@@ -1176,8 +1183,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_tail_b(const FieldArgs* __res
   __shared__ int64_t s_w[kFieldThreads / kWave];
   const int tid = threadIdx.x;
   block_exclusive<kFieldThreads>(tid < n ? args[tid].ctl->n_rare[SP] : 0, n, s_rs, s_w);
-  const int64_t nb = gridDim.x - nf;
-  rare_run<SP>(args, n, s_rs, (int64_t)(blockIdx.x - nf) + nb * tid, nb * kFieldThreads);
+  rare_segments<SP, kFieldThreads, VAR>(args, n, s_rs, (int)blockIdx.x - nf, (int)gridDim.x - nf);
 }
 
 // ---------------------------------------------------------------------------
@@ -1256,10 +1262,12 @@ hipError_t launch_particle_kernel(int kernel, int species, bool measure, const P
     else
       hipLaunchKernelGGL((k_emit<1>), dim3(c.grid_emit), dim3(kBlock), c.lds_emit, s, a);
   } else {
-    if (species == 0)
-      hipLaunchKernelGGL((k_rare<0>), dim3(c.grid_rare), dim3(kBlock), 0, s, a);
+    if (species == 0 && a.model)
+      hipLaunchKernelGGL((k_rare<0, true>), dim3(c.grid_rare), dim3(kBlock), 0, s, a);
+    else if (species == 0)
+      hipLaunchKernelGGL((k_rare<0, false>), dim3(c.grid_rare), dim3(kBlock), 0, s, a);
     else
-      hipLaunchKernelGGL((k_rare<1>), dim3(c.grid_rare), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_rare<1, false>), dim3(c.grid_rare), dim3(kBlock), 0, s, a);
   }
   return hipGetLastError();
 }
@@ -1291,7 +1299,7 @@ BatchLaunch batch_launch_config(int nx_max, int nbins_max, int num_cu, const int
 }
 
 hipError_t launch_batch_pass(int kernel, int species, bool measure, const PartArgs* args, int n,
-                             const BatchLaunch& c, hipStream_t s) {
+                             const BatchLaunch& c, hipStream_t s, bool variants) {
   if (n < 1 || n > kMaxBatch || species < 0 || species > 1) return hipErrorInvalidValue;
   const int m = (species == 0 && measure) ? 1 : 0;
   if (kernel == 0) {
@@ -1312,23 +1320,27 @@ hipError_t launch_batch_pass(int kernel, int species, bool measure, const PartAr
     else
       hipLaunchKernelGGL((k_emit_b<1>), dim3(c.grid_emit[1]), dim3(kBlock), c.lds_emit, s, args, n);
   } else {
-    if (species == 0)
-      hipLaunchKernelGGL((k_rare_b<0>), dim3(c.grid_rare), dim3(kBlock), 0, s, args, n);
+    if (species == 0 && variants)
+      hipLaunchKernelGGL((k_rare_b<0, true>), dim3(c.grid_rare), dim3(kBlock), 0, s, args, n);
+    else if (species == 0)
+      hipLaunchKernelGGL((k_rare_b<0, false>), dim3(c.grid_rare), dim3(kBlock), 0, s, args, n);
     else
-      hipLaunchKernelGGL((k_rare_b<1>), dim3(c.grid_rare), dim3(kBlock), 0, s, args, n);
+      hipLaunchKernelGGL((k_rare_b<1, false>), dim3(c.grid_rare), dim3(kBlock), 0, s, args, n);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_batch_tail(int species, const FieldArgs* f, int nf, const PartArgs* args, int n,
-                             int rare_blocks, hipStream_t s) {
+                             int rare_blocks, hipStream_t s, bool variants) {
   if (nf < 0 || nf > kMaxBatch || n < 0 || n > kMaxBatch || rare_blocks < 1)
     return hipErrorInvalidValue;
   const dim3 g(nf + rare_blocks);
-  if (species == 0)
-    hipLaunchKernelGGL((k_tail_b<0>), g, dim3(kFieldThreads), 0, s, f, nf, args, n);
+  if (species == 0 && variants)
+    hipLaunchKernelGGL((k_tail_b<0, true>), g, dim3(kFieldThreads), 0, s, f, nf, args, n);
+  else if (species == 0)
+    hipLaunchKernelGGL((k_tail_b<0, false>), g, dim3(kFieldThreads), 0, s, f, nf, args, n);
   else
-    hipLaunchKernelGGL((k_tail_b<1>), g, dim3(kFieldThreads), 0, s, f, nf, args, n);
+    hipLaunchKernelGGL((k_tail_b<1, false>), g, dim3(kFieldThreads), 0, s, f, nf, args, n);
   return hipGetLastError();
 }
 

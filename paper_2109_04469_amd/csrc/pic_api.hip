@@ -16,6 +16,7 @@ struct pic_batch {
   std::vector<pic_handle*> hs;
   hipStream_t stream;
   BatchLaunch launch;
+  bool variants;      // some discharge uses a method variant
   int chunk;          // steps per upload of argument blocks
   size_t step_bytes;  // argument bytes of one step (worst case)
   unsigned char* dev[2];
@@ -898,6 +899,9 @@ int pic_batch_create(pic_handle* const* handles, int n, void* workspace, uint64_
     tiles[1] += h->max_tiles[1];
   }
   b->launch = batch_launch_config(nx_max, nbins_max, handles[0]->num_cu, tiles);
+  b->variants = false;
+  for (pic_handle* h : b->hs)
+    if (h->p.flags & (PIC_FLAG_ANISO_ELASTIC | PIC_FLAG_OPAL_SHARING)) b->variants = true;
   for (int k = 0; k < 2; ++k) {
     b->dev[k] = static_cast<unsigned char*>(workspace) + k * half;
     b->host[k] = nullptr;
@@ -1021,24 +1025,24 @@ int pic_batch_step(pic_batch* b, int64_t n_steps) {
     for (int k = 0; k < m; ++k) {
       const StepLaunch& L = steps[k];
       if (L.nff) HIP_TRY(launch_batch_field(L.ff, L.nff, s));
-      if (L.nem) HIP_TRY(launch_batch_pass(0, 0, true, L.ed, L.nem, c, s));
-      if (n > L.nem) HIP_TRY(launch_batch_pass(0, 0, false, L.ed + L.nem, n - L.nem, c, s));
-      HIP_TRY(launch_batch_pass(1, 0, false, L.ed, n, c, s));
+      if (L.nem) HIP_TRY(launch_batch_pass(0, 0, true, L.ed, L.nem, c, s, b->variants));
+      if (n > L.nem) HIP_TRY(launch_batch_pass(0, 0, false, L.ed + L.nem, n - L.nem, c, s, b->variants));
+      HIP_TRY(launch_batch_pass(1, 0, false, L.ed, n, c, s, b->variants));
       if (L.nion) {
-        HIP_TRY(launch_batch_pass(2, 0, false, L.er, L.nion, c, s));
-        HIP_TRY(launch_batch_pass(0, 1, false, L.ia, L.nion, c, s));
-        HIP_TRY(launch_batch_pass(1, 1, false, L.ia, L.nion, c, s));
+        HIP_TRY(launch_batch_pass(2, 0, false, L.er, L.nion, c, s, b->variants));
+        HIP_TRY(launch_batch_pass(0, 1, false, L.ia, L.nion, c, s, b->variants));
+        HIP_TRY(launch_batch_pass(1, 1, false, L.ia, L.nion, c, s, b->variants));
       }
       if (L.tail) {
         if (L.nion) {
-          HIP_TRY(launch_batch_tail(1, L.fn, n, L.ia, L.nion, kTailRareBlocks, s));
-          if (L.nt0) HIP_TRY(launch_batch_pass(2, 0, false, L.t0, L.nt0, c, s));
+          HIP_TRY(launch_batch_tail(1, L.fn, n, L.ia, L.nion, kTailRareBlocks, s, b->variants));
+          if (L.nt0) HIP_TRY(launch_batch_pass(2, 0, false, L.t0, L.nt0, c, s, b->variants));
         } else {
-          HIP_TRY(launch_batch_tail(0, L.fn, n, L.t0, L.nt0, kTailRareBlocks, s));
+          HIP_TRY(launch_batch_tail(0, L.fn, n, L.t0, L.nt0, kTailRareBlocks, s, b->variants));
         }
       } else {
-        if (L.nt0) HIP_TRY(launch_batch_pass(2, 0, false, L.t0, L.nt0, c, s));
-        if (L.nion) HIP_TRY(launch_batch_pass(2, 1, false, L.ia, L.nion, c, s));
+        if (L.nt0) HIP_TRY(launch_batch_pass(2, 0, false, L.t0, L.nt0, c, s, b->variants));
+        if (L.nion) HIP_TRY(launch_batch_pass(2, 1, false, L.ia, L.nion, c, s, b->variants));
       }
       // cell sorts: species 0 of every due discharge, then species 1 (the
       // two species of a discharge share its sort counters)

@@ -178,10 +178,11 @@ struct BatchLaunch {
 // max_tiles: the largest number of tiles a pass of each species can have,
 // summed over the discharges
 BatchLaunch batch_launch_config(int nx_max, int nbins_max, int num_cu, const int64_t max_tiles[2]);
+// variants: some discharge of the list uses a method variant (model != 0)
 hipError_t launch_batch_pass(int kernel, int species, bool measure, const PartArgs* args, int n,
-                             const BatchLaunch& c, hipStream_t s);
+                             const BatchLaunch& c, hipStream_t s, bool variants);
 hipError_t launch_batch_tail(int species, const FieldArgs* f, int nf, const PartArgs* args, int n,
-                             int rare_blocks, hipStream_t s);
+                             int rare_blocks, hipStream_t s, bool variants);
 hipError_t launch_batch_field(const FieldArgs* f, int n, hipStream_t s);
 hipError_t launch_sort(const SortArgs& a, hipStream_t s);
 // n independent sorts (args in device memory, each with its own counters);
