@@ -584,3 +584,20 @@ def test_launch_shape_does_not_change_results():
         assert np.array_equal(d.counters(), ds[0].counters())
     kd, ke = ds[0].tune(10)
     assert kd >= 1 and ke >= 1 and ds[0].sync() == 0
+
+
+def test_batch_rejects_bad_handle_lists():
+    import torch
+
+    from paper_2109_04469_amd import Batch, Discharge, PicError
+
+    w = workloads.scaled(workloads.get("c1_small"), 500)
+    xs = xsec.argon_synthetic()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = Discharge(w["params"], xs, stream=s1)
+    b = Discharge(w["params"], xs, stream=s2)
+    c = Discharge(w["params"], xs, stream=s1)
+    for bad in ([a, b], [a, a], []):
+        with pytest.raises(PicError):
+            Batch(bad)
+    Batch([a, c]).close()
