@@ -339,7 +339,9 @@ def main():
         del d
         torch.cuda.empty_cache()
         out["sweep"] = sweep_measurement(torch, args.sweep_steps, log=log)
-    out["warm_start"] = None
+    out["warm_start"] = {
+        "not_run": "the warm-start study takes about 10 GPU-minutes; run bench.py --warm-start "
+                   "(results of a previous run in profiles/warm_start_study.md)"}
     if args.warm_start:
         from paper_2109_04469_amd import warmstart
 

@@ -7,7 +7,7 @@ of discharges (their density profiles of both species, mean electron energy
 profile and EEPF, the diagnostics of Sec. 3) predicts those averages from the
 six discharge parameters, and a new discharge is loaded from the prediction
 (pic_load_profile) instead of from a uniform plasma. The plain cold start
-remains both the fallback (when a prediction is unusable) and the judge: the
+remains both the fallback (when a prediction is unusable) and the yardstick: the
 converged averages of a long cold run are the reference the warm run is
 measured against.
 
