@@ -237,14 +237,18 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
 
 // The tiles t_begin, t_begin + t_step, ... below t_end of one particle pass
 // of discharge a: push, wall and candidacy decisions, decision codes, tile
-// totals and the deposit of the new positions. sH (and, measuring, sEW) are
-// all zero on entry and on exit; sE holds a's field.
+// totals and the deposit of the new positions. The waves do not wait for
+// each other inside the loop: each adds its share of a tile's totals to
+// a.tcnt (zeroed by the previous pass) with one atomic, and the deposits
+// collect in LDS until one flush at the end. sH (and, measuring, sEW) are all
+// zero on entry and on exit; sE holds a's field; s_lo > s_hi on entry and on
+// exit, and the caller synchronises the workgroup before the next call.
 template <int SP, bool MEASURE>
 __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int t_end, int t_step,
                                              int64_t n_push, int64_t n_tot, const double* sE,
                                              unsigned long long* sH, double* sEW,
-                                             unsigned int* sEEPF, uint32_t (*s_tot)[kDB / kWave],
-                                             int& s_lo, int& s_hi, unsigned long long* s_cnt) {
+                                             unsigned int* sEEPF, int& s_lo, int& s_hi,
+                                             unsigned long long* s_cnt) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
@@ -255,10 +259,10 @@ __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int
   const bool no_coll = a.no_coll != 0;
   const uint64_t cand_thr = no_coll ? 0ull : a.pcoll_thr;
 
+  int jlo = INT_MAX, jhi = -1;
   for (int t = t_begin; t < t_end; t += t_step) {
     const int64_t base = (int64_t)t * kTile;
     uint32_t own = 0, births = 0, rares = 0;
-    int jlo = INT_MAX, jhi = -1;
     // each thread takes runs of four consecutive slots: 16-byte loads, one
     // Philox block for the four candidacy draws, one 4-byte code store
 #pragma unroll
@@ -375,51 +379,49 @@ __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int
       }
     }
 
-    // tile totals and the touched deposit range
-    own = wave_sum<unsigned int>(own);
-    births = wave_sum<unsigned int>(births);
-    rares = wave_sum<unsigned int>(rares);
-    jlo = wave_min(jlo);
-    jhi = wave_max(jhi);
-    if (lane == 0) {
-      s_tot[0][wave] = own;
-      s_tot[1][wave] = births;
-      s_tot[2][wave] = rares;
-      atomicMin(&s_lo, jlo);
-      atomicMax(&s_hi, jhi);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      uint64_t o = 0, b = 0, r = 0;
-      for (int w = 0; w < kDB / kWave; ++w) {
-        o += s_tot[0][w];
-        b += s_tot[1][w];
-        r += s_tot[2][w];
-      }
-      a.tcnt[t] = o | (b << 16) | (r << 32);
-    }
-    const int lo = s_lo, hi = s_hi;  // lo > hi when the tile deposited nothing
-    for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += kDB) {
-      const unsigned long long v = sH[j];
-      if (v) {
-        atomicAdd(&a.dep_own[j], v);
-        sH[j] = 0ull;
-      }
-      if (MEASURE) {
-        const double e = sEW[j];
-        if (e != 0.0) {
-          atomicAdd(&a.acc_ew[j], e);
-          sEW[j] = 0.0;
-        }
-      }
-    }
-    __syncthreads();  // s_lo, s_hi and s_tot have been read
-    if (tid == 0) {
-      s_lo = INT_MAX;
-      s_hi = -1;
-    }
-    __syncthreads();
+    // this wave's share of the tile totals (each field stays below 2^16)
+    const unsigned long long tot = wave_sum<unsigned long long>(
+        (unsigned long long)own | ((unsigned long long)births << 16) |
+        ((unsigned long long)rares << 32));
+    if (lane == 0 && tot) atomicAdd(&a.tcnt[t], tot);
   }
+
+  // one flush of the deposit range touched by this workgroup's tiles
+  jlo = wave_min(jlo);
+  jhi = wave_max(jhi);
+  if (lane == 0) {
+    atomicMin(&s_lo, jlo);
+    atomicMax(&s_hi, jhi);
+  }
+  __syncthreads();
+  const int lo = s_lo, hi = s_hi;  // lo > hi when nothing was deposited
+  for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += kDB) {
+    const unsigned long long v = sH[j];
+    if (v) {
+      atomicAdd(&a.dep_own[j], v);
+      sH[j] = 0ull;
+    }
+    if (MEASURE) {
+      const double e = sEW[j];
+      if (e != 0.0) {
+        atomicAdd(&a.acc_ew[j], e);
+        sEW[j] = 0.0;
+      }
+    }
+  }
+  __syncthreads();  // s_lo and s_hi have been read
+  if (tid == 0) {
+    s_lo = INT_MAX;
+    s_hi = -1;
+  }
+}
+
+// Zeroes this workgroup's share of the tile totals buffer of the next pass
+// of discharge a (the previous pass of this species read it).
+__device__ __forceinline__ void clear_next_totals(const PartArgs& a) {
+  for (int64_t i = (int64_t)blockIdx.x * kDB + threadIdx.x; i < a.max_tiles;
+       i += (int64_t)gridDim.x * kDB)
+    a.tcnt_next[i] = 0ull;
 }
 
 template <int SP, bool MEASURE>
@@ -431,13 +433,14 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
   double* sEW = reinterpret_cast<double*>(sH + nx);                 // MEASURE
   unsigned int* sEEPF = reinterpret_cast<unsigned int*>(sEW + nx);  // MEASURE
 
-  __shared__ uint32_t s_tot[3][kDB / kWave];
   __shared__ int s_lo, s_hi;
   __shared__ unsigned long long s_cnt[NCOUNTERS];
 
   const int tid = threadIdx.x;
   DevCtl* ctl = a.ctl;
   const int par = a.parity;
+
+  clear_next_totals(a);
 
   for (int j = tid; j < nx; j += kDB) {
     sE[j] = a.E[j];
@@ -470,7 +473,7 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
   __syncthreads();
 
   decide_tiles<SP, MEASURE>(a, blockIdx.x, ntiles, gridDim.x, n_push, n_tot, sE, sH, sEW, sEEPF,
-                            s_tot, s_lo, s_hi, s_cnt);
+                            s_lo, s_hi, s_cnt);
 
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
   if (MEASURE) {
@@ -1025,13 +1028,13 @@ __global__ __launch_bounds__(kDB) void k_decide_b(const PartArgs* __restrict__ a
   double* sEW = reinterpret_cast<double*>(sH + nx_max);                 // MEASURE
   unsigned int* sEEPF = reinterpret_cast<unsigned int*>(sEW + nx_max);  // MEASURE
 
-  __shared__ uint32_t s_tot[3][kDB / kWave];
   __shared__ int s_lo, s_hi;
   __shared__ unsigned long long s_cnt[NCOUNTERS];
   __shared__ int64_t s_ts[kMaxBatch + 1];
   __shared__ int64_t s_w[kDB / kWave];
 
   const int tid = threadIdx.x;
+  for (int d = 0; d < n; ++d) clear_next_totals(args[d]);
   for (int j = tid; j < nx_max; j += kDB) {
     sH[j] = 0ull;
     if (MEASURE) sEW[j] = 0.0;
@@ -1073,7 +1076,7 @@ __global__ __launch_bounds__(kDB) void k_decide_b(const PartArgs* __restrict__ a
     for (int j = tid; j < a.nx; j += kDB) sE[j] = a.E[j];
     __syncthreads();
     decide_tiles<SP, MEASURE>(a, (int)(t - ts), (int)(se - ts), 1, n_push, n_tot, sE, sH, sEW,
-                              sEEPF, s_tot, s_lo, s_hi, s_cnt);
+                              sEEPF, s_lo, s_hi, s_cnt);
     // this discharge's event counts and EEPF counts
     if (tid < NCOUNTERS) {
       if (s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);

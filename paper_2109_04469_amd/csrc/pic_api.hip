@@ -47,7 +47,7 @@ double fedf_ion_emax(double rf_voltage_v) {
 }
 
 struct Layout {
-  size_t ctl, part[2][2][2], pid[2][2], pool[2][2][2], codes[2], tcnt[2], rq[2], dep_e[2], dep_i[2], rho, phi, E[2], cum[2], th_cp,
+  size_t ctl, part[2][2][2], pid[2][2], pool[2][2][2], codes[2], tcnt[2][2], rq[2], dep_e[2], dep_i[2], rho, phi, E[2], cum[2], th_cp,
       th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, fedf[2], sort_cnt, sort_seg, total;
   int64_t max_tiles[2];
   int sort_blocks;
@@ -100,7 +100,7 @@ Layout make_layout(const pic_params* p, const pic_xsec* xs) {
       for (int q = 0; q < 2; ++q) L.pool[s][b][q] = take((size_t)pool_capacity(cap) * 8);
     }
     L.codes[s] = take((size_t)cap);
-    L.tcnt[s] = take((size_t)L.max_tiles[s] * sizeof(uint64_t));
+    for (int b = 0; b < 2; ++b) L.tcnt[s][b] = take((size_t)L.max_tiles[s] * sizeof(uint64_t));
     L.rq[s] = take((size_t)cap * 16);
   }
   for (int b = 0; b < 2; ++b) L.dep_e[b] = take((size_t)nx * 8);
@@ -237,7 +237,10 @@ PartArgs particle_args(pic_handle* h, int sp, int parity) {
   }
   a.cum = h->cum[sp];
   a.ctl = h->ctl;
-  a.tcnt = h->tcnt[sp];
+  // tile totals are summed with atomics into a buffer the previous pass of
+  // this species zeroed; this pass zeroes the other one
+  a.tcnt = h->tcnt[sp][h->tsel[sp]];
+  a.tcnt_next = h->tcnt[sp][h->tsel[sp] ^ 1];
   a.rq = h->rq[sp];
   a.codes = h->codes[sp];
   a.acc_ew = h->acc_ew;
@@ -396,11 +399,13 @@ StepPlan plan_step(pic_handle* h, bool field_ready, bool last) {
   q.measure = h->measuring != 0;
   q.ae = particle_args(h, 0, par);
   h->cur[0] ^= 1;
+  h->tsel[0] ^= 1;
   q.pend_sp = 0;
   if (q.ion) {
     // the ions take this step's ionization ions with their velocities
     q.ai = particle_args(h, 1, par);
     h->cur[1] ^= 1;
+    h->tsel[1] ^= 1;
     h->cur_hi ^= 1;
     q.pend_sp = 1;
   }
@@ -688,7 +693,8 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
     }
     h->pcap[s] = pool_capacity(p->capacity[s]);
     h->codes[s] = reinterpret_cast<uint8_t*>(w + L.codes[s]);
-    h->tcnt[s] = reinterpret_cast<uint64_t*>(w + L.tcnt[s]);
+    for (int b = 0; b < 2; ++b) h->tcnt[s][b] = reinterpret_cast<uint64_t*>(w + L.tcnt[s][b]);
+    h->tsel[s] = 0;
     h->rq[s] = reinterpret_cast<uint4*>(w + L.rq[s]);
     h->max_tiles[s] = L.max_tiles[s];
     h->cum[s] = reinterpret_cast<double*>(w + L.cum[s]);

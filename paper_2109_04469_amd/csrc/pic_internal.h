@@ -70,6 +70,7 @@ struct PartArgs {
   const double* cum;              // cumulative nu tables, nproc x ntab
   DevCtl* ctl;
   uint64_t* tcnt;   // per tile: outputs | births << 16 | queued slots << 32
+  uint64_t* tcnt_next;  // the other totals buffer: zeroed here for the next pass
   uint4* rq;        // queued slots: (slot, code, output slot, birth rank)
   uint8_t* codes;
   double* acc_ew;                // CIC-weighted energy (electrons, measuring)
@@ -249,7 +250,8 @@ struct pic_handle {
   double* pool[2][2][2];  // [species][buffer][vy, vz]
   int64_t pcap[2];        // pool entries per buffer
   uint8_t* codes[2];
-  uint64_t* tcnt[2];
+  uint64_t* tcnt[2][2];  // per species, two buffers used by alternate passes
+  int tsel[2];           // the buffer the next pass of each species adds into
   uint4* rq[2];
   int64_t max_tiles[2];
   int64_t* dep_e[2];
