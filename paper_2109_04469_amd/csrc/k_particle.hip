@@ -1034,7 +1034,11 @@ __global__ __launch_bounds__(kDB) void k_decide_b(const PartArgs* __restrict__ a
   __shared__ int64_t s_w[kDB / kWave];
 
   const int tid = threadIdx.x;
-  for (int d = 0; d < n; ++d) clear_next_totals(args[d]);
+  // workgroup d zeroes the next totals buffer of discharge d
+  for (int d = blockIdx.x; d < n; d += gridDim.x) {
+    const PartArgs& a = args[d];
+    for (int64_t i = tid; i < a.max_tiles; i += kDB) a.tcnt_next[i] = 0ull;
+  }
   for (int j = tid; j < nx_max; j += kDB) {
     sH[j] = 0ull;
     if (MEASURE) sEW[j] = 0.0;
