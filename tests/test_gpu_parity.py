@@ -485,6 +485,48 @@ def test_batched_launches_equal_single_runs():
     b.close()
 
 
+def test_alternating_single_and_batched_steps():
+    # the tile-total buffers alternate between the passes of a species
+    # whichever launch path runs them: single steps, batch steps and single
+    # steps again give the bits of single steps throughout
+    import torch
+
+    from paper_2109_04469_amd import Batch, Discharge
+    from pic_inputs import sweep
+
+    sw = sweep.draw(3, seed=12, particles=(3_000, 30_000))
+    sw[1]["params"]["ion_subcycle"] = 3
+    init = sweep.initial_states(sw, seed=8)
+    xs = xsec.argon_synthetic()
+    stream = torch.cuda.Stream()
+    ds = [Discharge(w["params"], xs, stream=stream) for w in sw]
+    for d, st in zip(ds, init):
+        for sp in (0, 1):
+            d.set_state(sp, *st[sp], step=0)
+    b = Batch(ds)
+    for d in ds:
+        d.step(7)
+    b.step(11)
+    ds[0].step(4)
+    ds[1].step(4)
+    ds[2].step(4)
+    b.step(9)
+    for d in ds:
+        d.step(5)
+    torch.cuda.synchronize()
+    for w, st, d in zip(sw, init, ds):
+        assert d.sync() == 0
+        alone = Discharge(w["params"], xs)
+        for sp in (0, 1):
+            alone.set_state(sp, *st[sp], step=0)
+        alone.step(36)
+        assert alone.sync() == 0
+        for sp in (0, 1):
+            assert_state_equal(d.get_state(sp), alone.get_state(sp), what=f"{w['name']} sp {sp}")
+        assert np.array_equal(d.counters(), alone.counters())
+    b.close()
+
+
 def test_electrode_diagnostics_match_oracle():
     # Sec. 3.3 diagnostics over 40 measured steps of an evolving discharge
     # with reflection, emission and collisions: arrivals, absorptions and
