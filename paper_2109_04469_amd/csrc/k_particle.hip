@@ -37,6 +37,25 @@
 
 namespace pic {
 
+// Copies a field of nx values into LDS, PER loads of each thread issued
+// before its first store (one memory round trip per PER strides of the
+// workgroup instead of one per stride).
+template <int NT, int PER>
+__device__ __forceinline__ void stage_field(double* sE, const double* E, int nx) {
+  for (int j0 = (int)threadIdx.x; j0 < nx; j0 += PER * NT) {
+    double v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int j = j0 + k * NT;
+      v[k] = j < nx ? E[j] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int j = j0 + k * NT;
+      if (j < nx) sE[j] = v[k];
+    }
+  }
+}
 // Code bit used between the two kernels only: an Ar+ collision candidate
 // whose process (which needs a thermal atom velocity) is chosen in k_emit.
 // k_emit replaces it with the process bits, so a code read by the caller has
@@ -442,8 +461,8 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
 
   clear_next_totals(a);
 
+  stage_field<kDB, (kMaxNx + kDB - 1) / kDB>(sE, a.E, nx);
   for (int j = tid; j < nx; j += kDB) {
-    sE[j] = a.E[j];
     sH[j] = 0ull;
     if (MEASURE) sEW[j] = 0.0;
   }
@@ -556,12 +575,21 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
   DevCtl* ctl = a.ctl;
   const int par = a.parity;
   // outputs, births and queued slots of all earlier tiles
+  // (eight loads per thread in flight at a time)
   unsigned long long po = 0, pb = 0, pr = 0;
-  for (int t = tid; t < t0; t += kBlock) {
-    const uint64_t v = a.tcnt[t];
-    po += v & 0xFFFFull;
-    pb += (v >> 16) & 0xFFFFull;
-    pr += v >> 32;
+  for (int tb = 0; tb < t0; tb += 8 * kBlock) {
+    uint64_t v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = tb + u * kBlock + tid;
+      v[u] = t < t0 ? a.tcnt[t] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      po += v[u] & 0xFFFFull;
+      pb += (v[u] >> 16) & 0xFFFFull;
+      pr += v[u] >> 32;
+    }
   }
   po = wave_sum<unsigned long long>(po);
   pb = wave_sum<unsigned long long>(pb);
@@ -733,7 +761,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   const int t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
   if (t0 >= t1) return;
 
-  for (int j = tid; j < a.nx; j += kBlock) sE[j] = a.E[j];
+  stage_field<kBlock, (kMaxNx + kBlock - 1) / kBlock>(sE, a.E, a.nx);
   if (tid == 0) s_qn = 0;
   emit_tiles<SP>(a, t0, t1, ntiles, n_tot, bbase, sE, s_wtot, s_woff, s_red, s_agg, s_qn);
 }
@@ -1077,7 +1105,7 @@ __global__ __launch_bounds__(kDB) void k_decide_b(const PartArgs* __restrict__ a
     pass_slots<SP>(a, n_push, n_tot);
     n_push = uniform64(n_push);
     n_tot = uniform64(n_tot);
-    for (int j = tid; j < a.nx; j += kDB) sE[j] = a.E[j];
+    stage_field<kDB, 2>(sE, a.E, a.nx);  // (register budget of the batched kernel)
     __syncthreads();
     decide_tiles<SP, MEASURE>(a, (int)(t - ts), (int)(se - ts), 1, n_push, n_tot, sE, sH, sEW,
                               sEEPF, s_lo, s_hi, s_cnt);
@@ -1133,7 +1161,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_b(const PartArgs* __restrict__ 
     n_tot = uniform64(n_tot);
     const DevCtl* ctl = a.ctl;
     const int64_t bbase = uniform64(SP == 0 ? ctl->n_i[a.parity] : ctl->e_out);
-    for (int j = tid; j < a.nx; j += kBlock) sE[j] = a.E[j];
+    stage_field<kBlock, 4>(sE, a.E, a.nx);  // (register budget of the batched kernel)
     if (tid == 0) s_qn = 0;
     emit_tiles<SP>(a, (int)(t - ts), (int)(se - ts), (int)(tn - ts), n_tot, bbase, sE, s_wtot,
                    s_woff, s_red, s_agg, s_qn);
