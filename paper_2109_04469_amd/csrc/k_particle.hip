@@ -610,8 +610,9 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
   for (int t = t0; t < t1; ++t) {
     const int64_t base = (int64_t)t * kTile;
     // pairs of consecutive slots per lane: 16-byte loads of x and v_x, an
-    // 8-byte load of the two pool indices, one 2-byte load of the codes; all
-    // loads are issued before the tile's scan
+    // 8-byte load of the two pool indices, one 2-byte load of the codes;
+    // each pair row's count and wave scan follow its loads (issuing every
+    // row's loads first measured slower)
     uint32_t code[kPPT], loc[kEPairs];
     double px[kPPT], pvx[kPPT];
     uint32_t pid[kPPT];
