@@ -155,6 +155,33 @@ def test_single_step_fixed_field(n, seed, step, subcycle):
     assert np.array_equal(fg["dep_i"], fo["dep_i"])
 
 
+@pytest.mark.parametrize("empty", [0, 1, 2])
+def test_empty_species_steps_match_oracle(empty):
+    # no electrons (ion impacts emit the first ones), no ions (ionizations
+    # make the first ones) or neither: three steps, each from the state the
+    # last one left, against the oracle stepped alongside
+    p, xs, init, E, L, ve, vi = _single_step_case(4000, 8, 0, 1, FIXED_E, R=0.2, gamma=0.4)
+    z = np.zeros(0)
+    for sp in ((0,) if empty == 0 else (1,) if empty == 1 else (0, 1)):
+        init[sp] = (z, z, z, z)
+    gpu, ora = pair(p, xs, init, step=0, fixed_E=E)
+    for k in range(3):
+        # the GPU's counters restart with each set_state; the oracle's run on
+        oc0 = np.asarray(ora.counters()).copy()
+        gpu.step(1)
+        assert ora.step(1) == 0
+        assert gpu.sync() == 0
+        assert np.array_equal(gpu.counters(), np.asarray(ora.counters()) - oc0), f"step {k}"
+        for sp, vs in ((0, ve), (1, vi)):
+            assert np.array_equal(gpu.decisions(sp), ora.decisions(sp)), f"step {k} decisions {sp}"
+            assert_state_close(gpu.get_state(sp), ora.get_state(sp), L, vs, what=f"step {k} sp {sp}")
+        # the next step starts from the oracle's state on both sides
+        for sp in (0, 1):
+            gpu.set_state(sp, *ora.get_state(sp), step=k + 1)
+    if empty == 2:
+        assert gpu.count(0) == 0 and gpu.count(1) == 0
+
+
 def test_single_step_with_field_solve_thomas():
     # the whole step including deposit and Thomas solve, from an evolved state
     w = workloads.scaled(workloads.get("c1_small"), 6000)
