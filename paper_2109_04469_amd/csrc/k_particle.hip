@@ -270,7 +270,6 @@ __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int
                                              unsigned long long* s_cnt) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wave = tid / kWave;
   const int nx = a.nx;
   const uint32_t step = a.step;
   const double inv_dx = a.inv_dx;
