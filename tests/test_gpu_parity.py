@@ -84,7 +84,7 @@ def _field_case(mode_flags, n_cells, seed):
     return gpu.get_field(), ora.get_field(), p
 
 
-@pytest.mark.parametrize("n_cells", [128, 512, 2048])
+@pytest.mark.parametrize("n_cells", [128, 512, 2048, 4096])
 def test_field_thomas_bitwise(n_cells):
     fg, fo, _ = _field_case(THOMAS, n_cells, 5)
     assert np.array_equal(fg["rho"], fo["rho"])
@@ -92,7 +92,7 @@ def test_field_thomas_bitwise(n_cells):
     assert np.array_equal(fg["E"], fo["E"])
 
 
-@pytest.mark.parametrize("n_cells", [128, 512, 2048])
+@pytest.mark.parametrize("n_cells", [128, 512, 2048, 4096])
 def test_field_exact_solver_within_rounding(n_cells):
     # The default solver sums the integer deposits exactly and rounds a few
     # times per node; the oracle's Thomas recurrence accumulates rounding over
@@ -139,10 +139,12 @@ def _single_step_case(n, seed, step, subcycle, flags, R=0.3, gamma=0.25, n_cells
     return p, xs, {0: e, 1: i}, E, L, ve, vi
 
 
-@pytest.mark.parametrize("n,seed,step,subcycle", [
-    (5000, 1, 0, 1), (20_011, 2, 3, 1), (7_777, 3, 10, 5), (7_777, 4, 11, 5), (1, 5, 0, 1)])
-def test_single_step_fixed_field(n, seed, step, subcycle):
-    p, xs, init, E, L, ve, vi = _single_step_case(n, seed, step, subcycle, FIXED_E)
+@pytest.mark.parametrize("n,seed,step,subcycle,n_cells", [
+    (5000, 1, 0, 1, 128), (20_011, 2, 3, 1, 128), (7_777, 3, 10, 5, 128), (7_777, 4, 11, 5, 128),
+    (1, 5, 0, 1, 128), (30_001, 6, 2, 1, 4096)])
+def test_single_step_fixed_field(n, seed, step, subcycle, n_cells):
+    # the last case uses the largest grid (4096 cells, 4097 nodes)
+    p, xs, init, E, L, ve, vi = _single_step_case(n, seed, step, subcycle, FIXED_E, n_cells=n_cells)
     gpu, ora = pair(p, xs, init, step=step, fixed_E=E)
     gpu.step(1)
     ora.step(1)
