@@ -556,6 +556,41 @@ def test_alternating_single_and_batched_steps():
     b.close()
 
 
+def test_batch_with_empty_populations():
+    # a batch in which one discharge has no electrons and another no ions
+    # at the start equals the same discharges stepped alone
+    import torch
+
+    from paper_2109_04469_amd import Batch, Discharge
+    from pic_inputs import sweep
+
+    sw = sweep.draw(3, seed=13, particles=(2_000, 8_000))
+    init = sweep.initial_states(sw, seed=9)
+    z = np.zeros(0)
+    init[0][0] = (z, z, z, z)
+    init[1][1] = (z, z, z, z)
+    xs = xsec.argon_synthetic()
+    stream = torch.cuda.Stream()
+    ds = [Discharge(w["params"], xs, stream=stream) for w in sw]
+    for d, st in zip(ds, init):
+        for sp in (0, 1):
+            d.set_state(sp, *st[sp], step=0)
+    b = Batch(ds)
+    b.step(25)
+    torch.cuda.synchronize()
+    for w, st, d in zip(sw, init, ds):
+        assert d.sync() == 0
+        alone = Discharge(w["params"], xs)
+        for sp in (0, 1):
+            alone.set_state(sp, *st[sp], step=0)
+        alone.step(25)
+        assert alone.sync() == 0
+        for sp in (0, 1):
+            assert_state_equal(d.get_state(sp), alone.get_state(sp), what=f"{w['name']} sp {sp}")
+        assert np.array_equal(d.counters(), alone.counters())
+    b.close()
+
+
 def test_electrode_diagnostics_match_oracle():
     # Sec. 3.3 diagnostics over 40 measured steps of an evolving discharge
     # with reflection, emission and collisions: arrivals, absorptions and
