@@ -397,10 +397,17 @@ __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int
       }
     }
 
-    // this wave's share of the tile totals (each field stays below 2^16)
-    const unsigned long long tot = wave_sum<unsigned long long>(
-        (unsigned long long)own | ((unsigned long long)births << 16) |
-        ((unsigned long long)rares << 32));
+    // this wave's share of the tile totals, summed in one 32-bit word (per
+    // wave at most 2 * 4 * kDGroups * 64 outputs and half as many births or
+    // queued slots: 11, 11 and 10 bits) with lane moves, then widened to the
+    // totals' layout
+    static_assert(kDGroups <= 2, "wave totals fit the 11/11/10-bit fields");
+    const uint32_t packed = own | (births << 11) | (rares << 22);
+    const uint32_t ws =
+        (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(packed), kWave - 1);
+    const unsigned long long tot = (unsigned long long)(ws & 0x7FFu) |
+                                   ((unsigned long long)((ws >> 11) & 0x7FFu) << 16) |
+                                   ((unsigned long long)(ws >> 22) << 32);
     if (lane == 0 && tot) atomicAdd(&a.tcnt[t], tot);
   }
 
@@ -652,7 +659,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
           cnt += oc.own | (oc.birth << 16);
         }
       }
-      const uint32_t inc = wave_incl_scan<unsigned int>(cnt);
+      const uint32_t inc = wave_incl_scan_dpp(cnt);
       loc[k] = inc - cnt;
       if (lane == kWave - 1) s_wtot[k][wave] = inc;
     }
@@ -663,7 +670,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       uint32_t* wo = &s_woff[0][0];
       constexpr int nseg = kEPairs * (kBlock / kWave);
       const uint32_t v = lane < nseg ? wt[lane] : 0u;
-      const uint32_t inc = wave_incl_scan<unsigned int>(v);
+      const uint32_t inc = wave_incl_scan_dpp(v);
       if (lane < nseg) wo[lane] = inc - v;
       if (lane == nseg - 1) s_agg = inc;
     }

@@ -161,6 +161,21 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
   return v;
 }
 
+// The same inclusive scan of 32-bit values with data-parallel lane moves
+// (no LDS traffic): shifts by 1, 2, 4 and 8 lanes inside each row of 16, then
+// the last lane of row 0 (and of row 2) added to row 1 (and row 3), then
+// the last lane of row 1 added to rows 2 and 3. Lanes without a source add 0.
+__device__ __forceinline__ uint32_t wave_incl_scan_dpp(uint32_t v) {
+  int x = (int)v;
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, true);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15, rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31, rows 2, 3
+  return (uint32_t)x;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
