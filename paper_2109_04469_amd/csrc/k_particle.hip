@@ -567,14 +567,18 @@ __device__ __forceinline__ void emit_empty(DevCtl* ctl, int par) {
 
 // The contiguous tiles [t0, t1) of a particle pass of discharge a (ntiles
 // tiles, n_tot slots): compacted outputs, queued rare slots and, at the last
-// tile, the pass's counts. sE holds a's field; s_qn is zero on entry.
+// tile, the pass's counts. sE holds a's field. The scan state (s_wtot,
+// s_woff, s_agg, s_qn) has two copies used by alternate tiles, so that a
+// tile needs two workgroup barriers: a tile's totals are added to the
+// prefix after the next tile's first barrier, when its queue counts are
+// complete. s_qn[0..1] are zero on entry and on return.
 template <int SP>
 __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, int ntiles,
                                            int64_t n_tot, int64_t bbase, const double* sE,
-                                           uint32_t (*s_wtot)[kBlock / kWave],
-                                           uint32_t (*s_woff)[kBlock / kWave],
-                                           uint64_t (*s_red)[kBlock / kWave], uint32_t& s_agg,
-                                           uint32_t& s_qn) {
+                                           uint32_t (*s_wtot)[kEPairs][kBlock / kWave],
+                                           uint32_t (*s_woff)[kEPairs][kBlock / kWave],
+                                           uint64_t (*s_red)[kBlock / kWave], uint32_t* s_agg,
+                                           uint32_t* s_qn) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
@@ -614,6 +618,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
   }
 
   for (int t = t0; t < t1; ++t) {
+    const int p = (t - t0) & 1;
     const int64_t base = (int64_t)t * kTile;
     // pairs of consecutive slots per lane: 16-byte loads of x and v_x, an
     // 8-byte load of the two pool indices, one 2-byte load of the codes;
@@ -661,24 +666,33 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       }
       const uint32_t inc = wave_incl_scan_dpp(cnt);
       loc[k] = inc - cnt;
-      if (lane == kWave - 1) s_wtot[k][wave] = inc;
+      if (lane == kWave - 1) s_wtot[p][k][wave] = inc;
     }
     __syncthreads();
+    if (t > t0) {
+      // the previous tile's totals: its queue counts are complete here
+      const uint32_t agg = s_agg[p ^ 1];
+      prefO += agg & 0xFFFFu;
+      prefB += agg >> 16;
+      prefR += s_qn[p ^ 1];
+    }
+    // this copy's count was read after the previous barrier by every thread
+    if (tid == 0) s_qn[p] = 0;
     if (wave == 0) {
       // offsets of the (pair row, wave) segments, row-major
-      const uint32_t* wt = &s_wtot[0][0];
-      uint32_t* wo = &s_woff[0][0];
+      const uint32_t* wt = &s_wtot[p][0][0];
+      uint32_t* wo = &s_woff[p][0][0];
       constexpr int nseg = kEPairs * (kBlock / kWave);
       const uint32_t v = lane < nseg ? wt[lane] : 0u;
       const uint32_t inc = wave_incl_scan_dpp(v);
       if (lane < nseg) wo[lane] = inc - v;
-      if (lane == nseg - 1) s_agg = inc;
+      if (lane == nseg - 1) s_agg[p] = inc;
     }
     __syncthreads();
 
 #pragma unroll
     for (int k = 0; k < kEPairs; ++k) {
-      uint32_t off = s_woff[k][wave] + loc[k];
+      uint32_t off = s_woff[p][k][wave] + loc[k];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int q = 2 * k + h;
@@ -691,7 +705,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         if (m) {
           // queue the slot for the rare work with its output slots
           uint32_t qb = 0;
-          if (lane == 0) qb = atomicAdd(&s_qn, (uint32_t)__popcll(m));
+          if (lane == 0) qb = atomicAdd(&s_qn[p], (uint32_t)__popcll(m));
           qb = __shfl(qb, 0);
           if (rare) {
             const int64_t pos = prefR + qb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
@@ -708,12 +722,16 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         if (in) off += oc.own | (oc.birth << 16);
       }
     }
-    __syncthreads();
-    const uint32_t agg = s_agg;
+  }
+  // the last tile's totals, then (at the pass's last tile) the pass's counts
+  __syncthreads();
+  if (t1 > t0) {
+    const int p = (t1 - 1 - t0) & 1;
+    const uint32_t agg = s_agg[p];
     prefO += agg & 0xFFFFu;
     prefB += agg >> 16;
-    prefR += s_qn;
-    if (t == ntiles - 1 && tid == 0) {
+    prefR += s_qn[p];
+    if (t1 - 1 == ntiles - 1 && tid == 0) {
       ctl->n_rare[SP] = prefR;
       if (SP == 0) {
         ctl->e_out = prefO;
@@ -735,19 +753,19 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       ctl->pool_n[other] += prefB;
       if (ctl->pool_n[SP] > a.pcap || ctl->pool_n[other] > a.bpcap) latch_error(ctl, kErrCapacity);
     }
-    __syncthreads();  // s_woff, s_agg and s_qn are reused by the next tile
-    if (tid == 0) s_qn = 0;
   }
+  __syncthreads();  // every thread has read s_agg and s_qn
+  if (tid == 0) s_qn[0] = s_qn[1] = 0u;
 }
 
 template <int SP>
 __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* sE = reinterpret_cast<double*>(smem);
-  __shared__ uint32_t s_wtot[kEPairs][kBlock / kWave];
-  __shared__ uint32_t s_woff[kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_wtot[2][kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_woff[2][kEPairs][kBlock / kWave];
   __shared__ uint64_t s_red[3][kBlock / kWave];
-  __shared__ uint32_t s_agg, s_qn;
+  __shared__ uint32_t s_agg[2], s_qn[2];
 
   const int tid = threadIdx.x;
   DevCtl* ctl = a.ctl;
@@ -769,7 +787,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   if (t0 >= t1) return;
 
   stage_field<kBlock, (kMaxNx + kBlock - 1) / kBlock>(sE, a.E, a.nx);
-  if (tid == 0) s_qn = 0;
+  if (tid == 0) s_qn[0] = s_qn[1] = 0u;
   emit_tiles<SP>(a, t0, t1, ntiles, n_tot, bbase, sE, s_wtot, s_woff, s_red, s_agg, s_qn);
 }
 
@@ -1138,10 +1156,10 @@ template <int SP>
 __global__ __launch_bounds__(kBlock) void k_emit_b(const PartArgs* __restrict__ args, int n) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* sE = reinterpret_cast<double*>(smem);
-  __shared__ uint32_t s_wtot[kEPairs][kBlock / kWave];
-  __shared__ uint32_t s_woff[kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_wtot[2][kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_woff[2][kEPairs][kBlock / kWave];
   __shared__ uint64_t s_red[3][kBlock / kWave];
-  __shared__ uint32_t s_agg, s_qn;
+  __shared__ uint32_t s_agg[2], s_qn[2];
   __shared__ int64_t s_ts[kMaxBatch + 1];
   __shared__ int64_t s_w[kBlock / kWave];
 
@@ -1169,7 +1187,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_b(const PartArgs* __restrict__ 
     const DevCtl* ctl = a.ctl;
     const int64_t bbase = uniform64(SP == 0 ? ctl->n_i[a.parity] : ctl->e_out);
     stage_field<kBlock, 4>(sE, a.E, a.nx);  // (register budget of the batched kernel)
-    if (tid == 0) s_qn = 0;
+    if (tid == 0) s_qn[0] = s_qn[1] = 0u;
     emit_tiles<SP>(a, (int)(t - ts), (int)(se - ts), (int)(tn - ts), n_tot, bbase, sE, s_wtot,
                    s_woff, s_red, s_agg, s_qn);
     t = se;
