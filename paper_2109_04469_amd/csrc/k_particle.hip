@@ -567,18 +567,17 @@ __device__ __forceinline__ void emit_empty(DevCtl* ctl, int par) {
 
 // The contiguous tiles [t0, t1) of a particle pass of discharge a (ntiles
 // tiles, n_tot slots): compacted outputs, queued rare slots and, at the last
-// tile, the pass's counts. sE holds a's field. The scan state (s_wtot,
-// s_woff, s_agg, s_qn) has two copies used by alternate tiles, so that a
-// tile needs two workgroup barriers: a tile's totals are added to the
-// prefix after the next tile's first barrier, when its queue counts are
-// complete. s_qn[0..1] are zero on entry and on return.
+// tile, the pass's counts. sE holds a's field. The per-wave totals of
+// outputs and births (s_wtot) and of queued slots (s_wr) have two copies
+// used by alternate tiles, and every wave scans a tile's totals itself, so
+// a tile needs one workgroup barrier; queued slots take their places in
+// slot order from the same scans.
 template <int SP>
 __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, int ntiles,
                                            int64_t n_tot, int64_t bbase, const double* sE,
                                            uint32_t (*s_wtot)[kEPairs][kBlock / kWave],
-                                           uint32_t (*s_woff)[kEPairs][kBlock / kWave],
-                                           uint64_t (*s_red)[kBlock / kWave], uint32_t* s_agg,
-                                           uint32_t* s_qn) {
+                                           uint32_t (*s_wr)[kEPairs][kBlock / kWave],
+                                           uint64_t (*s_red)[kBlock / kWave]) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
@@ -624,13 +623,13 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
     // 8-byte load of the two pool indices, one 2-byte load of the codes;
     // each pair row's count and wave scan follow its loads (issuing every
     // row's loads first measured slower)
-    uint32_t code[kPPT], loc[kEPairs];
+    uint32_t code[kPPT], loc[kEPairs], rloc[kEPairs];
     double px[kPPT], pvx[kPPT];
     uint32_t pid[kPPT];
 #pragma unroll
     for (int k = 0; k < kEPairs; ++k) {
       const int64_t s0 = base + k * (2 * kBlock) + 2 * tid;
-      uint32_t cnt = 0;
+      uint32_t cnt = 0, rcnt = 0;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         code[2 * k + h] = 0;
@@ -662,37 +661,36 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         if (c & 0x100u) {
           const Outcome oc = outcome<SP>(c);
           cnt += oc.own | (oc.birth << 16);
+          rcnt += oc.rare ? 1u : 0u;
         }
       }
       const uint32_t inc = wave_incl_scan_dpp(cnt);
+      const uint32_t rinc = wave_incl_scan_dpp(rcnt);
       loc[k] = inc - cnt;
-      if (lane == kWave - 1) s_wtot[p][k][wave] = inc;
+      rloc[k] = rinc - rcnt;
+      if (lane == kWave - 1) {
+        s_wtot[p][k][wave] = inc;
+        s_wr[p][k][wave] = rinc;
+      }
     }
     __syncthreads();
-    if (t > t0) {
-      // the previous tile's totals: its queue counts are complete here
-      const uint32_t agg = s_agg[p ^ 1];
-      prefO += agg & 0xFFFFu;
-      prefB += agg >> 16;
-      prefR += s_qn[p ^ 1];
-    }
-    // this copy's count was read after the previous barrier by every thread
-    if (tid == 0) s_qn[p] = 0;
-    if (wave == 0) {
-      // offsets of the (pair row, wave) segments, row-major
-      const uint32_t* wt = &s_wtot[p][0][0];
-      uint32_t* wo = &s_woff[p][0][0];
-      constexpr int nseg = kEPairs * (kBlock / kWave);
-      const uint32_t v = lane < nseg ? wt[lane] : 0u;
-      const uint32_t inc = wave_incl_scan_dpp(v);
-      if (lane < nseg) wo[lane] = inc - v;
-      if (lane == nseg - 1) s_agg[p] = inc;
-    }
-    __syncthreads();
+    // every wave scans the tile's segment totals (segment k * nw + w) itself,
+    // so no second barrier is needed; the other copy of the totals belongs
+    // to the next tile
+    constexpr int nw = kBlock / kWave;
+    constexpr int nseg = kEPairs * nw;
+    const uint32_t sv = lane < nseg ? (&s_wtot[p][0][0])[lane] : 0u;
+    const uint32_t sr = lane < nseg ? (&s_wr[p][0][0])[lane] : 0u;
+    const uint32_t si = wave_incl_scan_dpp(sv);
+    const uint32_t sri = wave_incl_scan_dpp(sr);
+    const uint32_t tile_ob = (uint32_t)__builtin_amdgcn_readlane((int)si, nseg - 1);
+    const uint32_t tile_r = (uint32_t)__builtin_amdgcn_readlane((int)sri, nseg - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
 
 #pragma unroll
     for (int k = 0; k < kEPairs; ++k) {
-      uint32_t off = s_woff[p][k][wave] + loc[k];
+      uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)(si - sv), k * nw + wv) + loc[k];
+      uint32_t roff = (uint32_t)__builtin_amdgcn_readlane((int)(sri - sr), k * nw + wv) + rloc[k];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int q = 2 * k + h;
@@ -701,17 +699,12 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         const Outcome oc = outcome<SP>(c);
         const bool rare = in && oc.rare;
         const int64_t slot = base + k * (2 * kBlock) + 2 * tid + h;
-        const uint64_t m = __ballot(rare);
-        if (m) {
+        if (rare) {
           // queue the slot for the rare work with its output slots
-          uint32_t qb = 0;
-          if (lane == 0) qb = atomicAdd(&s_qn[p], (uint32_t)__popcll(m));
-          qb = __shfl(qb, 0);
-          if (rare) {
-            const int64_t pos = prefR + qb + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            a.rq[pos] = make_uint4((uint32_t)slot, c & 0xFFu, (uint32_t)(prefO + (off & 0xFFFFu)),
-                                   (uint32_t)(prefB + (off >> 16)));
-          }
+          a.rq[prefR + roff] = make_uint4((uint32_t)slot, c & 0xFFu,
+                                          (uint32_t)(prefO + (off & 0xFFFFu)),
+                                          (uint32_t)(prefB + (off >> 16)));
+          ++roff;
         }
         if (in && !rare && oc.own) {
           const int64_t dest = prefO + (int64_t)(off & 0xFFFFu);
@@ -722,16 +715,10 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         if (in) off += oc.own | (oc.birth << 16);
       }
     }
-  }
-  // the last tile's totals, then (at the pass's last tile) the pass's counts
-  __syncthreads();
-  if (t1 > t0) {
-    const int p = (t1 - 1 - t0) & 1;
-    const uint32_t agg = s_agg[p];
-    prefO += agg & 0xFFFFu;
-    prefB += agg >> 16;
-    prefR += s_qn[p];
-    if (t1 - 1 == ntiles - 1 && tid == 0) {
+    prefO += tile_ob & 0xFFFFu;
+    prefB += tile_ob >> 16;
+    prefR += tile_r;
+    if (t == ntiles - 1 && tid == 0) {
       ctl->n_rare[SP] = prefR;
       if (SP == 0) {
         ctl->e_out = prefO;
@@ -754,8 +741,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       if (ctl->pool_n[SP] > a.pcap || ctl->pool_n[other] > a.bpcap) latch_error(ctl, kErrCapacity);
     }
   }
-  __syncthreads();  // every thread has read s_agg and s_qn
-  if (tid == 0) s_qn[0] = s_qn[1] = 0u;
+  __syncthreads();  // the field and the totals may be reused by the caller
 }
 
 template <int SP>
@@ -763,9 +749,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* sE = reinterpret_cast<double*>(smem);
   __shared__ uint32_t s_wtot[2][kEPairs][kBlock / kWave];
-  __shared__ uint32_t s_woff[2][kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_wr[2][kEPairs][kBlock / kWave];
   __shared__ uint64_t s_red[3][kBlock / kWave];
-  __shared__ uint32_t s_agg[2], s_qn[2];
 
   const int tid = threadIdx.x;
   DevCtl* ctl = a.ctl;
@@ -787,8 +772,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   if (t0 >= t1) return;
 
   stage_field<kBlock, (kMaxNx + kBlock - 1) / kBlock>(sE, a.E, a.nx);
-  if (tid == 0) s_qn[0] = s_qn[1] = 0u;
-  emit_tiles<SP>(a, t0, t1, ntiles, n_tot, bbase, sE, s_wtot, s_woff, s_red, s_agg, s_qn);
+  emit_tiles<SP>(a, t0, t1, ntiles, n_tot, bbase, sE, s_wtot, s_wr, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1157,9 +1141,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_b(const PartArgs* __restrict__ 
   extern __shared__ __align__(16) unsigned char smem[];
   double* sE = reinterpret_cast<double*>(smem);
   __shared__ uint32_t s_wtot[2][kEPairs][kBlock / kWave];
-  __shared__ uint32_t s_woff[2][kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_wr[2][kEPairs][kBlock / kWave];
   __shared__ uint64_t s_red[3][kBlock / kWave];
-  __shared__ uint32_t s_agg[2], s_qn[2];
   __shared__ int64_t s_ts[kMaxBatch + 1];
   __shared__ int64_t s_w[kBlock / kWave];
 
@@ -1187,9 +1170,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_b(const PartArgs* __restrict__ 
     const DevCtl* ctl = a.ctl;
     const int64_t bbase = uniform64(SP == 0 ? ctl->n_i[a.parity] : ctl->e_out);
     stage_field<kBlock, 4>(sE, a.E, a.nx);  // (register budget of the batched kernel)
-    if (tid == 0) s_qn[0] = s_qn[1] = 0u;
     emit_tiles<SP>(a, (int)(t - ts), (int)(se - ts), (int)(tn - ts), n_tot, bbase, sE, s_wtot,
-                   s_woff, s_red, s_agg, s_qn);
+                   s_wr, s_red);
     t = se;
     d = next_owner(s_ts, n, d + 1, t);
   }
