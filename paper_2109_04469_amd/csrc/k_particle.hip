@@ -572,9 +572,9 @@ __device__ __forceinline__ void emit_empty(DevCtl* ctl, int par) {
 // used by alternate tiles, and every wave scans a tile's totals itself, so
 // a tile needs one workgroup barrier; queued slots take their places in
 // slot order from the same scans.
-template <int SP>
+template <int SP, int STAGE_PER>
 __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, int ntiles,
-                                           int64_t n_tot, int64_t bbase, const double* sE,
+                                           int64_t n_tot, int64_t bbase, double* sE,
                                            uint32_t (*s_wtot)[kEPairs][kBlock / kWave],
                                            uint32_t (*s_wr)[kEPairs][kBlock / kWave],
                                            uint64_t (*s_red)[kBlock / kWave]) {
@@ -583,15 +583,21 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
   const int wave = tid / kWave;
   DevCtl* ctl = a.ctl;
   const int par = a.parity;
-  // outputs, births and queued slots of all earlier tiles
-  // (eight loads per thread in flight at a time)
+  // outputs, births and queued slots of all earlier tiles (eight loads per
+  // thread in flight at a time), and a's field staged into sE while the
+  // first of those loads are in flight
   unsigned long long po = 0, pb = 0, pr = 0;
+  bool staged = false;
   for (int tb = 0; tb < t0; tb += 8 * kBlock) {
     uint64_t v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int t = tb + u * kBlock + tid;
       v[u] = t < t0 ? a.tcnt[t] : 0ull;
+    }
+    if (!staged) {
+      stage_field<kBlock, STAGE_PER>(sE, a.E, a.nx);
+      staged = true;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -600,6 +606,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       pr += v[u] >> 32;
     }
   }
+  if (!staged) stage_field<kBlock, STAGE_PER>(sE, a.E, a.nx);
   po = wave_sum<unsigned long long>(po);
   pb = wave_sum<unsigned long long>(pb);
   pr = wave_sum<unsigned long long>(pr);
@@ -771,8 +778,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   const int t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
   if (t0 >= t1) return;
 
-  stage_field<kBlock, (kMaxNx + kBlock - 1) / kBlock>(sE, a.E, a.nx);
-  emit_tiles<SP>(a, t0, t1, ntiles, n_tot, bbase, sE, s_wtot, s_wr, s_red);
+  emit_tiles<SP, (kMaxNx + kBlock - 1) / kBlock>(a, t0, t1, ntiles, n_tot, bbase, sE, s_wtot,
+                                                  s_wr, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1169,8 +1176,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_b(const PartArgs* __restrict__ 
     n_tot = uniform64(n_tot);
     const DevCtl* ctl = a.ctl;
     const int64_t bbase = uniform64(SP == 0 ? ctl->n_i[a.parity] : ctl->e_out);
-    stage_field<kBlock, 4>(sE, a.E, a.nx);  // (register budget of the batched kernel)
-    emit_tiles<SP>(a, (int)(t - ts), (int)(se - ts), (int)(tn - ts), n_tot, bbase, sE, s_wtot,
+    // (four staging loads per thread: register budget of the batched kernel)
+    emit_tiles<SP, 4>(a, (int)(t - ts), (int)(se - ts), (int)(tn - ts), n_tot, bbase, sE, s_wtot,
                    s_wr, s_red);
     t = se;
     d = next_owner(s_ts, n, d + 1, t);
