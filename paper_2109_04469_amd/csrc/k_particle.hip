@@ -544,6 +544,9 @@ __device__ __forceinline__ void reload(const PartArgs& a, const double* E, int64
   repush(a, E, c, x, vx);
 }
 
+// tile totals each thread reads at once per step of a strided run
+constexpr int kStrideLoads = 8;
+
 // pairs of consecutive slots per lane and tile in k_emit
 constexpr int kEPairs = kPPT / 2;
 static_assert(kPPT % 2 == 0, "k_emit takes pairs of slots");
@@ -565,18 +568,21 @@ __device__ __forceinline__ void emit_empty(DevCtl* ctl, int par) {
   }
 }
 
-// The contiguous tiles [t0, t1) of a particle pass of discharge a (ntiles
-// tiles, n_tot slots): compacted outputs, queued rare slots and, at the last
-// tile, the pass's counts. sE holds a's field. The per-wave totals of
+// The tiles t0, t0 + t_step, ... below t1 of a particle pass of discharge a
+// (ntiles tiles, n_tot slots): compacted outputs, queued rare slots and, at
+// the last tile, the pass's counts. With t_step > 1 the totals of the tiles
+// between two of this workgroup's tiles are summed while the first of them is
+// loaded, so the prefix reaches the next one without another pass. sE holds a's field. The per-wave totals of
 // outputs and births (s_wtot) and of queued slots (s_wr) have two copies
 // used by alternate tiles, and every wave scans a tile's totals itself, so
 // a tile needs one workgroup barrier; queued slots take their places in
 // slot order from the same scans.
 template <int SP, int STAGE_PER>
-__device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, int ntiles,
-                                           int64_t n_tot, int64_t bbase, double* sE,
+__device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, int t_step,
+                                           int ntiles, int64_t n_tot, int64_t bbase, double* sE,
                                            uint32_t (*s_wtot)[kEPairs][kBlock / kWave],
                                            uint32_t (*s_wr)[kEPairs][kBlock / kWave],
+                                           uint32_t (*s_ps)[3][kBlock / kWave],
                                            uint64_t (*s_red)[kBlock / kWave]) {
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -623,9 +629,25 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
     prefR += (int64_t)s_red[2][w];
   }
 
-  for (int t = t0; t < t1; ++t) {
-    const int p = (t - t0) & 1;
+  for (int t = t0; t < t1; t += t_step) {
+    const int p = ((t - t0) / t_step) & 1;
     const int64_t base = (int64_t)t * kTile;
+    // strided runs: the totals of tiles t .. t + t_step - 1 carry the prefix
+    // to this workgroup's next tile (loads issued with the tile's own)
+    uint32_t nso = 0, nsb = 0, nsr = 0;
+    if (t_step > 1 && t + t_step < t1) {
+      const int ue = min(t + t_step, ntiles);
+      for (int c0 = t; c0 < ue; c0 += kStrideLoads * kBlock) {  // once for grids <= 2048
+#pragma unroll
+        for (int k = 0; k < kStrideLoads; ++k) {
+          const int u = c0 + k * kBlock + tid;
+          const uint64_t v = u < ue ? a.tcnt[u] : 0ull;
+          nso += (uint32_t)(v & 0xFFFFull);
+          nsb += (uint32_t)((v >> 16) & 0xFFFFull);
+          nsr += (uint32_t)(v >> 32);
+        }
+      }
+    }
     // pairs of consecutive slots per lane: 16-byte loads of x and v_x, an
     // 8-byte load of the two pool indices, one 2-byte load of the codes;
     // each pair row's count and wave scan follow its loads (issuing every
@@ -680,6 +702,15 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         s_wr[p][k][wave] = rinc;
       }
     }
+    if (t_step > 1 && t + t_step < t1) {
+      const uint32_t wo = wave_incl_scan_dpp(nso), wb = wave_incl_scan_dpp(nsb),
+                     wr = wave_incl_scan_dpp(nsr);
+      if (lane == kWave - 1) {
+        s_ps[p][0][wave] = wo;
+        s_ps[p][1][wave] = wb;
+        s_ps[p][2][wave] = wr;
+      }
+    }
     __syncthreads();
     // every wave scans the tile's segment totals (segment k * nw + w) itself,
     // so no second barrier is needed; the other copy of the totals belongs
@@ -722,6 +753,20 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         if (in) off += oc.own | (oc.birth << 16);
       }
     }
+    if (t_step > 1 && t + t_step < t1) {
+      // the next tile of this workgroup is t + t_step
+      int64_t ao = 0, ab = 0, ar = 0;
+#pragma unroll
+      for (int w = 0; w < kBlock / kWave; ++w) {
+        ao += s_ps[p][0][w];
+        ab += s_ps[p][1][w];
+        ar += s_ps[p][2][w];
+      }
+      prefO += ao;
+      prefB += ab;
+      prefR += ar;
+      continue;
+    }
     prefO += tile_ob & 0xFFFFu;
     prefB += tile_ob >> 16;
     prefR += tile_r;
@@ -757,6 +802,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   double* sE = reinterpret_cast<double*>(smem);
   __shared__ uint32_t s_wtot[2][kEPairs][kBlock / kWave];
   __shared__ uint32_t s_wr[2][kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_ps[2][3][kBlock / kWave];
   __shared__ uint64_t s_red[3][kBlock / kWave];
 
   const int tid = threadIdx.x;
@@ -773,13 +819,24 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
     if (blockIdx.x == 0 && tid == 0) emit_empty<SP>(ctl, par);
     return;
   }
-  // this workgroup's contiguous run of tiles
-  const int t0 = uniform32((int)((int64_t)ntiles * blockIdx.x / gridDim.x));
-  const int t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
+  // this workgroup's tiles. Electrons: a contiguous run (measured faster for
+  // them). Ions, whose arrays were last touched several steps ago: tiles
+  // blockIdx.x, blockIdx.x + gridDim.x, ..., which keeps all workgroups
+  // inside one moving window of the arrays (measured 12 % faster for them).
+  int t0, t1, t_step;
+  if (SP == 0) {
+    t0 = uniform32((int)((int64_t)ntiles * blockIdx.x / gridDim.x));
+    t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
+    t_step = 1;
+  } else {
+    t0 = blockIdx.x;
+    t1 = ntiles;
+    t_step = gridDim.x;
+  }
   if (t0 >= t1) return;
 
-  emit_tiles<SP, (kMaxNx + kBlock - 1) / kBlock>(a, t0, t1, ntiles, n_tot, bbase, sE, s_wtot,
-                                                  s_wr, s_red);
+  emit_tiles<SP, (kMaxNx + kBlock - 1) / kBlock>(a, t0, t1, t_step, ntiles, n_tot, bbase, sE,
+                                                  s_wtot, s_wr, s_ps, s_red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1149,6 +1206,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_b(const PartArgs* __restrict__ 
   double* sE = reinterpret_cast<double*>(smem);
   __shared__ uint32_t s_wtot[2][kEPairs][kBlock / kWave];
   __shared__ uint32_t s_wr[2][kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_ps[2][3][kBlock / kWave];
   __shared__ uint64_t s_red[3][kBlock / kWave];
   __shared__ int64_t s_ts[kMaxBatch + 1];
   __shared__ int64_t s_w[kBlock / kWave];
@@ -1177,8 +1235,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_b(const PartArgs* __restrict__ 
     const DevCtl* ctl = a.ctl;
     const int64_t bbase = uniform64(SP == 0 ? ctl->n_i[a.parity] : ctl->e_out);
     // (four staging loads per thread: register budget of the batched kernel)
-    emit_tiles<SP, 4>(a, (int)(t - ts), (int)(se - ts), (int)(tn - ts), n_tot, bbase, sE, s_wtot,
-                   s_wr, s_red);
+    emit_tiles<SP, 4>(a, (int)(t - ts), (int)(se - ts), 1, (int)(tn - ts), n_tot, bbase, sE,
+                      s_wtot, s_wr, s_ps, s_red);
     t = se;
     d = next_owner(s_ts, n, d + 1, t);
   }
