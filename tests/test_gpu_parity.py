@@ -692,6 +692,37 @@ def test_launch_shape_does_not_change_results():
     assert kd >= 1 and ke >= 1 and ds[0].sync() == 0
 
 
+def test_workgroups_taking_several_tiles_match_oracle():
+    # More tiles than workgroups: 700,001 slots per species make 342 tiles of
+    # 2048, against 256 workgroups at one per CU, so a workgroup takes two
+    # tiles (the ion emit carries its prefix over the tiles in between), and
+    # the last tile is ragged. The default shape (one tile per workgroup) and
+    # the oracle must agree with it.
+    from paper_2109_04469_amd import Discharge
+
+    w = workloads.scaled(workloads.get("c1_small"), 700_001)
+    p = dict(w["params"], flags=RECORD, reflection=0.3, gamma_see=0.2)
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w, seed=33)
+    L = p["gap_m"]
+    gpu, ora = pair(p, xs, init)
+    gpu.set_launch(1, 1)
+    ref = Discharge(p, xs, "cuda:0")
+    for sp in (0, 1):
+        ref.set_state(sp, *init[sp], step=0)
+    for k in range(3):
+        gpu.step(1)
+        ref.step(1)
+        assert ora.step(1) == 0
+        for sp, vs in ((0, _vth(2.0, ME)), (1, _vth(0.03, MAR))):
+            assert np.array_equal(gpu.decisions(sp), ora.decisions(sp)), f"step {k} species {sp}"
+            assert_state_close(gpu.get_state(sp), ora.get_state(sp), L, vs, rtol=1e-10,
+                               what=f"step {k} species {sp}")
+            assert_state_equal(ref.get_state(sp), gpu.get_state(sp), what=f"default shape, step {k}")
+        assert np.array_equal(gpu.counters(), ora.counters()), f"step {k}"
+        assert np.array_equal(ref.counters(), gpu.counters()), f"step {k}"
+
+
 def test_batch_rejects_bad_handle_lists():
     import torch
 
