@@ -49,7 +49,7 @@ BYTES_PER_PARTICLE_STEP = 64
 # rocprofv3 FETCH_SIZE (x2, the factor a plain copy of known size gives)
 # and WRITE_SIZE (x1) at c3; to be re-measured whenever the pass's kernels
 # change (None when not measured for the current kernels)
-PASS_TRAFFIC_BYTES_PER_PARTICLE = 60.13
+PASS_TRAFFIC_BYTES_PER_PARTICLE = 60.15
 
 DESCRIPTIONS = {
     "c3_large_lowp": ("gap 6.7 cm, 2048 cells, dt=T_RF/8000, 13.56 MHz, 500 V, 2 Pa, gamma 0.2, R 0.5, "
