@@ -17,6 +17,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+OMP_PATH = os.path.join(HERE, "liboracle_omp.so")
 SOURCES = [os.path.join(HERE, "pic_oracle.c"), os.path.join(HERE, "philox.c"),
            os.path.join(HERE, "warm_oracle.c")]
 CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
@@ -25,67 +26,97 @@ NCOUNTERS = 16
 F_NO_FIELD, F_FIXED_E, F_NO_COLL, F_IMMOBILE_IONS, F_RECORD = 1, 2, 4, 8, 16
 
 
-def build(force=True, extra_flags=()):
-    """Compile liboracle.so with gcc (FP contraction off, no fast-math)."""
-    if not force and os.path.exists(LIB_PATH):
-        newest = max(os.path.getmtime(s) for s in SOURCES)
-        if os.path.getmtime(LIB_PATH) >= newest:
-            return LIB_PATH
-    tmp = LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", *CFLAGS, *extra_flags, "-o", tmp, *SOURCES, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB_PATH)
+def build(force=True, extra_flags=(), openmp=True):
+    """Compile liboracle.so with gcc (FP contraction off, no fast-math) and,
+    with openmp, the same sources with -fopenmp as liboracle_omp.so (a pass
+    split over threads in slot-ordered runs; used only to time the oracle
+    on several cores)."""
+    _compile(LIB_PATH, force, extra_flags)
+    if openmp:
+        _compile(OMP_PATH, force, ("-fopenmp", *extra_flags))
     return LIB_PATH
 
 
+def _compile(path, force, flags):
+    if not force and os.path.exists(path):
+        newest = max(os.path.getmtime(s) for s in SOURCES)
+        if os.path.getmtime(path) >= newest:
+            return
+    tmp = path + ".tmp%d" % os.getpid()
+    cmd = ["gcc", *CFLAGS, *flags, "-o", tmp, *SOURCES, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, path)
+
+
 _lib = None
+_lib_omp = None
 
 
 def lib():
+    """The plain single-threaded oracle (the checker)."""
     global _lib
     if _lib is None:
-        build(force=False)
-        L = ctypes.CDLL(LIB_PATH)
-        P = ctypes.c_void_p
-        d = ctypes.POINTER(ctypes.c_double)
-        i64p = ctypes.POINTER(ctypes.c_int64)
-        u32p = ctypes.POINTER(ctypes.c_uint32)
-        u64p = ctypes.POINTER(ctypes.c_uint64)
-        L.ora_philox4x32_10.argtypes = [u32p, u32p, u32p]
-        L.ora_philox4x64_10.argtypes = [u64p, u64p, u64p]
-        L.ora_create.restype = P
-        L.ora_create.argtypes = [ctypes.POINTER(OraParams), d, d, d, d, d]
-        L.ora_free.argtypes = [P]
-        L.ora_set_state.argtypes = [P, ctypes.c_int, d, d, d, d, ctypes.c_int64, ctypes.c_int64]
-        L.ora_get_count.argtypes = [P, ctypes.c_int]
-        L.ora_get_count.restype = ctypes.c_int64
-        L.ora_get_step.argtypes = [P]
-        L.ora_get_step.restype = ctypes.c_int64
-        L.ora_get_state.argtypes = [P, ctypes.c_int, d, d, d, d]
-        L.ora_set_field.argtypes = [P, d]
-        L.ora_get_field.argtypes = [P, d, d, d, i64p, i64p]
-        L.ora_get_counters.argtypes = [P, i64p]
-        L.ora_get_decisions.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]
-        L.ora_get_decisions.restype = ctypes.c_int64
-        L.ora_get_derived.argtypes = [P, d]
-        L.ora_measure.argtypes = [P, ctypes.c_int]
-        L.ora_moments.argtypes = [P, d, d, d, d, i64p, ctypes.c_int]
-        L.ora_step.argtypes = [P, ctypes.c_int64]
-        L.ora_step.restype = ctypes.c_int
-        L.ora_deposit.argtypes = [P]
-        L.ora_solve_field.argtypes = [P]
-        L.ora_cell.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, i64p, d, i64p]
-        L.ora_deposit_array.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int64, d, i64p]
-        L.ora_thomas.argtypes = [ctypes.c_int64, d, d, d, d, d]
-        L.ora_poisson.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, d, d]
-        L.ora_efield.argtypes = [ctypes.c_int32, ctypes.c_double, d, d, d]
-        L.ora_wall_raw.argtypes = [P, i64p, i64p, d, i64p, i64p, i64p, d]
-        L.ora_load_profile.argtypes = [d, d, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
-                                       ctypes.c_int64, d, d, d, d]
-        L.ora_load_profile.restype = ctypes.c_int
-        _lib = L
+        _compile(LIB_PATH, False, ())
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+def lib_openmp():
+    """The OpenMP build of the same sources (timing only); its thread count
+    follows OMP_NUM_THREADS, read when the library is first loaded."""
+    global _lib_omp
+    if _lib_omp is None:
+        _compile(OMP_PATH, False, ("-fopenmp",))
+        _lib_omp = _declare(ctypes.CDLL(OMP_PATH))
+    return _lib_omp
+
+
+def threads(openmp=False):
+    return int((lib_openmp() if openmp else lib()).ora_threads())
+
+
+def _declare(L):
+    """Argument and result types of the library's entry points."""
+    P = ctypes.c_void_p
+    d = ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    L.ora_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    L.ora_philox4x64_10.argtypes = [u64p, u64p, u64p]
+    L.ora_create.restype = P
+    L.ora_create.argtypes = [ctypes.POINTER(OraParams), d, d, d, d, d]
+    L.ora_free.argtypes = [P]
+    L.ora_set_state.argtypes = [P, ctypes.c_int, d, d, d, d, ctypes.c_int64, ctypes.c_int64]
+    L.ora_get_count.argtypes = [P, ctypes.c_int]
+    L.ora_get_count.restype = ctypes.c_int64
+    L.ora_get_step.argtypes = [P]
+    L.ora_get_step.restype = ctypes.c_int64
+    L.ora_get_state.argtypes = [P, ctypes.c_int, d, d, d, d]
+    L.ora_set_field.argtypes = [P, d]
+    L.ora_get_field.argtypes = [P, d, d, d, i64p, i64p]
+    L.ora_get_counters.argtypes = [P, i64p]
+    L.ora_get_decisions.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]
+    L.ora_get_decisions.restype = ctypes.c_int64
+    L.ora_get_derived.argtypes = [P, d]
+    L.ora_measure.argtypes = [P, ctypes.c_int]
+    L.ora_moments.argtypes = [P, d, d, d, d, i64p, ctypes.c_int]
+    L.ora_step.argtypes = [P, ctypes.c_int64]
+    L.ora_step.restype = ctypes.c_int
+    L.ora_deposit.argtypes = [P]
+    L.ora_solve_field.argtypes = [P]
+    L.ora_cell.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, i64p, d, i64p]
+    L.ora_deposit_array.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_int64, d, i64p]
+    L.ora_thomas.argtypes = [ctypes.c_int64, d, d, d, d, d]
+    L.ora_poisson.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, d, d]
+    L.ora_efield.argtypes = [ctypes.c_int32, ctypes.c_double, d, d, d]
+    L.ora_wall_raw.argtypes = [P, i64p, i64p, d, i64p, i64p, i64p, d]
+    L.ora_load_profile.argtypes = [d, d, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                   ctypes.c_int64, d, d, d, d]
+    L.ora_load_profile.restype = ctypes.c_int
+    L.ora_threads.restype = ctypes.c_int
+    return L
 
 
 class OraParams(ctypes.Structure):
@@ -214,8 +245,8 @@ class Oracle:
     """One discharge on the CPU oracle. params: a workload parameter dict;
     xs: a pic_inputs.xsec.XsecTables."""
 
-    def __init__(self, params, xs):
-        L = lib()
+    def __init__(self, params, xs, openmp=False):
+        L = lib_openmp() if openmp else lib()
         p = OraParams()
         for name, _ in OraParams._fields_:
             if name in ("ntab", "dv_e", "dv_i", "exc_threshold_ev", "ion_threshold_ev"):

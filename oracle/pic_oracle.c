@@ -23,6 +23,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
@@ -206,6 +209,10 @@ void ora_cell(int32_t nx, double inv_dx, double x, int64_t* j_out, double* f_out
  * node j in units of 2^-32 superparticle (exact integer sums). */
 void ora_deposit_array(int32_t nx, double inv_dx, int64_t n, const double* x, int64_t* dep) {
   memset(dep, 0, sizeof(int64_t) * (size_t)nx);
+  /* integer sums: any order (threads of an OpenMP build) gives the same */
+#ifdef _OPENMP
+#pragma omp parallel for reduction(+ : dep[:nx])
+#endif
   for (int64_t i = 0; i < n; i++) {
     int64_t j, w1;
     double f;
@@ -437,6 +444,16 @@ int ora_set_state(ora_sim* s, int species, const double* x, const double* vx, co
 int64_t ora_get_count(const ora_sim* s, int species) { return s->sp[species].n; }
 int64_t ora_get_step(const ora_sim* s) { return s->step; }
 
+/* Threads a particle pass runs on: 1 in the plain build, the OpenMP
+ * thread count in a build with -fopenmp. */
+int ora_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 void ora_get_state(const ora_sim* s, int species, double* x, double* vx, double* vy, double* vz) {
   const ora_species* q = &s->sp[species];
   memcpy(x, q->x, sizeof(double) * (size_t)q->n);
@@ -563,6 +580,9 @@ static void plist_push(plist* l, double x, double vx, double vy, double vz) {
   }
   l->n++;
 }
+static void plist_append(plist* l, const plist* m) {
+  for (int64_t k = 0; k < m->n; k++) plist_push(l, m->x[k], m->vx[k], m->vy[k], m->vz[k]);
+}
 
 /* Linear interpolation of a cumulative collision-frequency table at speed v.
  * Beyond the last table speed the last entry is used (a constant frequency,
@@ -578,6 +598,232 @@ static int table_lookup(const ora_sim* s, int sp, double v, double* nu) {
   double t = tv - (double)k;
   for (int q = 0; q < s->nproc[sp]; q++) nu[q] = (1.0 - t) * s->cum[sp][q][k] + t * s->cum[sp][q][k + 1];
   return 0;
+}
+
+/* Outputs of one run of consecutive slots of a particle pass, in slot
+ * order: the species' survivors (an ionization electron right after its
+ * parent), the ions born from electron impact ionization and the secondary
+ * electrons emitted by ion impacts, with the run's event counts and
+ * electrode diagnostics. A pass is one run in the plain build; an OpenMP
+ * build splits it into one run per thread and joins the runs in slot order,
+ * which gives the same lists and integer counts. */
+typedef struct {
+  plist out, ibirth, se;
+  int64_t counters[NCOUNT];
+  int64_t wall_hits[2][2], wall_abs[2][2], ioniz_meas;
+  double wall_esum[2][2];
+  int64_t* fedf[2];
+  int err;
+} ora_run;
+
+/* Steps (3)-(6) of Sec. 2 for slot i of species sp: field at the particle,
+ * leap-frog push, the walls and the null-collision Monte Carlo step; the
+ * outputs go to run c. */
+static void step_slot(ora_sim* s, int sp, int64_t i, ora_run* c) {
+  const ora_params* p = &s->p;
+  const int32_t nx = s->nx;
+  const double L = s->L;
+  const ora_species* q = &s->sp[sp];
+  const double dts = s->dts[sp];
+  double x = q->x[i], vx = q->vx[i], vy = q->vy[i], vz = q->vz[i];
+  uint8_t code = 0x80;
+  /* (3) field at the particle: linear interpolation */
+  int64_t j, w1;
+  double f;
+  ora_cell(nx, s->inv_dx, x, &j, &f, &w1);
+  double Ep = (1.0 - f) * s->E[j] + f * s->E[j + 1];
+  /* (4) leap-frog: v(n+1/2) = v(n-1/2) + (q/m) E dt, x(n+1) = x(n) + v dt */
+  vx = vx + s->acc[sp] * Ep;
+  x = x + vx * dts;
+  uint32_t r0[4];
+  draw(s, i, sp, 0, r0);
+  int alive = 1;
+  /* (5) boundaries */
+  if (!isfinite(x) || !isfinite(vx)) {
+    c->err = c->err ? c->err : ORA_EUNSTABLE;
+    alive = 0;
+    code |= 1;
+  } else if (x < 0.0 || x > L) {
+    /* arrival at an electrode: count it, its impact energy and its
+     * energy bin (Sec. 3.3); absorption is added below */
+    int wall = x < 0.0 ? 0 : 1;
+    if (s->measuring) {
+      double eps = s->ek[sp] * (vx * vx + vy * vy + vz * vz);
+      c->wall_hits[sp][wall]++;
+      c->wall_esum[sp][wall] += eps;
+      int64_t b = (int64_t)(eps * ((double)p->eepf_bins / s->fedf_emax[sp]));
+      if (b >= 0 && b < p->eepf_bins) c->fedf[sp][(int64_t)wall * p->eepf_bins + b]++;
+    }
+    double ub = u01(r0[0]);
+    if (sp == 0) {
+      if (ub < p->reflection) {
+        /* elastic (specular) reflection */
+        x = (x < 0.0) ? -x : (L + L) - x;
+        vx = -vx;
+        if (x < 0.0 || x > L) {
+          alive = 0;
+          code |= 4;
+          c->counters[C_REFLECT_LOST]++;
+        } else {
+          code |= 2;
+          c->counters[C_E_REFLECTED]++;
+        }
+      } else {
+        alive = 0;
+        code |= 1;
+        c->counters[C_E_ABSORBED]++;
+      }
+    } else {
+      alive = 0;
+      c->counters[C_I_ABSORBED]++;
+      if (ub < p->gamma_see) {
+        /* ion-induced secondary electron, emitted from the hit wall
+         * with a half-Maxwellian velocity at see_temp_ev */
+        uint32_t r3[4];
+        draw(s, i, 1, 3, r3);
+        double n1, n2, n3, dummy;
+        box_muller(u01(r3[0]), u01(r3[1]), &n1, &n2);
+        box_muller(u01(r3[2]), u01(r3[3]), &n3, &dummy);
+        double xw = (x < 0.0) ? 0.0 : L;
+        double vxs = s->sig_se * fabs(n1);
+        if (x > L) vxs = -vxs;
+        plist_push(&c->se, xw, vxs, s->sig_se * n2, s->sig_se * n3);
+        code |= 3;
+        c->counters[C_SE_EMITTED]++;
+      } else {
+        code |= 1;
+      }
+    }
+    if (s->measuring && !alive) c->wall_abs[sp][wall]++;
+  }
+  /* (6) null-collision Monte Carlo */
+  int child = 0;
+  double cx = 0, cvx = 0, cvy = 0, cvz = 0;
+  if (alive && !(p->flags & F_NO_COLL) && u01(candidacy_word(s, i, sp)) < s->pcoll[sp]) {
+    double nu[3];
+    if (sp == 0) {
+      c->counters[C_E_CAND]++;
+      double v2 = vx * vx + vy * vy + vz * vz;
+      double speed = sqrt(v2);
+      if (table_lookup(s, 0, speed, nu) != 0) c->counters[C_BEYOND]++;
+      {
+        double r = u01(r0[2]) * s->numax[0];
+        uint32_t r1[4];
+        if (r < nu[0]) {
+          /* elastic: two-body kinematics, atom at rest, isotropic in
+           * the centre-of-mass frame */
+          draw(s, i, 0, 1, r1);
+          double nx_, ny_, nz_;
+          if ((p->flags & F_ANISO) && speed > 0.0)
+            deflect(vx / speed, vy / speed, vz / speed, s->ek_e * v2, u01(r1[0]), u01(r1[1]),
+                    &nx_, &ny_, &nz_);
+          else
+            iso_dir(u01(r1[0]), u01(r1[1]), &nx_, &ny_, &nz_);
+          double g = s->mm_e * speed;
+          vx = s->mr_e * vx + g * nx_;
+          vy = s->mr_e * vy + g * ny_;
+          vz = s->mr_e * vz + g * nz_;
+          code |= 2 << 3;
+          c->counters[C_E_ELASTIC]++;
+        } else if (r < nu[1]) {
+          /* excitation: threshold energy lost, new direction isotropic */
+          draw(s, i, 0, 1, r1);
+          double eps = s->ek_e * v2 - p->exc_threshold_ev;
+          if (eps < 0.0) eps = 0.0;
+          double sp1 = sqrt(eps * s->ve_e);
+          double nx_, ny_, nz_;
+          iso_dir(u01(r1[0]), u01(r1[1]), &nx_, &ny_, &nz_);
+          vx = sp1 * nx_;
+          vy = sp1 * ny_;
+          vz = sp1 * nz_;
+          code |= 3 << 3;
+          c->counters[C_E_EXC]++;
+        } else if (r < nu[2]) {
+          /* ionization: the energy above threshold is shared
+           * uniformly between the scattered and the ejected electron,
+           * both isotropic; the new ion is thermal */
+          draw(s, i, 0, 1, r1);
+          uint32_t r2[4], r3[4];
+          draw(s, i, 0, 2, r2);
+          draw(s, i, 0, 3, r3);
+          double eps = s->ek_e * v2 - p->ion_threshold_ev;
+          if (eps < 0.0) eps = 0.0;
+          /* uniform sharing, or (variant) the Opal et al. form whose
+           * cumulative distribution on [0, eps/2] is
+           * atan(e / w) / atan(eps / (2 w)) */
+          double e_ej = (p->flags & F_OPAL) ? OPAL_W * tan(u01(r2[0]) * atan(eps / (2.0 * OPAL_W)))
+                                            : u01(r2[0]) * eps;
+          double e_sc = eps - e_ej;
+          double s_sc = sqrt(e_sc * s->ve_e);
+          double s_ej = sqrt(e_ej * s->ve_e);
+          double ax, ay, az, bx, by, bz;
+          iso_dir(u01(r1[0]), u01(r1[1]), &ax, &ay, &az);
+          iso_dir(u01(r1[2]), u01(r1[3]), &bx, &by, &bz);
+          vx = s_sc * ax;
+          vy = s_sc * ay;
+          vz = s_sc * az;
+          child = 1;
+          cx = x;
+          cvx = s_ej * bx;
+          cvy = s_ej * by;
+          cvz = s_ej * bz;
+          double n1, n2, n3, dummy;
+          box_muller(u01(r3[0]), u01(r3[1]), &n1, &n2);
+          box_muller(u01(r3[2]), u01(r3[3]), &n3, &dummy);
+          plist_push(&c->ibirth, x, s->sig_g * n1, s->sig_g * n2, s->sig_g * n3);
+          code |= 4 << 3;
+          c->counters[C_E_ION]++;
+          if (s->measuring) c->ioniz_meas++;
+        } else {
+          code |= 1 << 3;
+        }
+      }
+    } else {
+      /* Ar+ on a thermal Ar atom drawn for the candidate */
+      c->counters[C_I_CAND]++;
+      uint32_t r1[4];
+      draw(s, i, 1, 1, r1);
+      double n1, n2, n3, dummy;
+      box_muller(u01(r1[0]), u01(r1[1]), &n1, &n2);
+      box_muller(u01(r1[2]), u01(r1[3]), &n3, &dummy);
+      double ax = s->sig_g * n1, ay = s->sig_g * n2, az = s->sig_g * n3;
+      double gx = vx - ax, gy = vy - ay, gz = vz - az;
+      double g = sqrt(gx * gx + gy * gy + gz * gz);
+      if (table_lookup(s, 1, g, nu) != 0) c->counters[C_BEYOND]++;
+      {
+        double r = u01(r0[2]) * s->numax[1];
+        if (r < nu[0]) {
+          /* isotropic elastic in the centre-of-mass frame (equal masses) */
+          uint32_t r2[4];
+          draw(s, i, 1, 2, r2);
+          double ux, uy, uz;
+          iso_dir(u01(r2[0]), u01(r2[1]), &ux, &uy, &uz);
+          double hg = 0.5 * g;
+          vx = 0.5 * (vx + ax) + hg * ux;
+          vy = 0.5 * (vy + ay) + hg * uy;
+          vz = 0.5 * (vz + az) + hg * uz;
+          code |= 2 << 3;
+          c->counters[C_I_ISO]++;
+        } else if (r < nu[1]) {
+          /* backward scattering = symmetric charge transfer: the ion
+           * leaves with the atom's velocity */
+          vx = ax;
+          vy = ay;
+          vz = az;
+          code |= 3 << 3;
+          c->counters[C_I_BACK]++;
+        } else {
+          code |= 1 << 3;
+        }
+      }
+    }
+  }
+  if (p->flags & F_RECORD) s->codes[sp][i] = code;
+  if (alive) {
+    plist* out = &c->out;
+    plist_push(out, x, vx, vy, vz);
+    if (child) plist_push(out, cx, cvx, cvy, cvz);
+  }
 }
 
 int ora_step(ora_sim* s, int64_t nsteps) {
@@ -653,210 +899,52 @@ int ora_step(ora_sim* s, int64_t nsteps) {
 
     for (int sp = 0; sp < 2; sp++) {
       if (sp == 1 && !ion_step) break;
-      ora_species* q = &s->sp[sp];
-      const double dts = s->dts[sp];
+      const ora_species* q = &s->sp[sp];
       s->counters[sp == 0 ? C_E_PUSHED : C_I_PUSHED] += q->n;
-      for (int64_t i = 0; i < q->n; i++) {
-        double x = q->x[i], vx = q->vx[i], vy = q->vy[i], vz = q->vz[i];
-        uint8_t code = 0x80;
-        /* (3) field at the particle: linear interpolation */
-        int64_t j, w1;
-        double f;
-        ora_cell(nx, s->inv_dx, x, &j, &f, &w1);
-        double Ep = (1.0 - f) * s->E[j] + f * s->E[j + 1];
-        /* (4) leap-frog: v(n+1/2) = v(n-1/2) + (q/m) E dt, x(n+1) = x(n) + v dt */
-        vx = vx + s->acc[sp] * Ep;
-        x = x + vx * dts;
-        uint32_t r0[4];
-        draw(s, i, sp, 0, r0);
-        int alive = 1;
-        /* (5) boundaries */
-        if (!isfinite(x) || !isfinite(vx)) {
-          s->err = s->err ? s->err : ORA_EUNSTABLE;
-          alive = 0;
-          code |= 1;
-        } else if (x < 0.0 || x > L) {
-          /* arrival at an electrode: count it, its impact energy and its
-           * energy bin (Sec. 3.3); absorption is added below */
-          int wall = x < 0.0 ? 0 : 1;
-          if (s->measuring) {
-            double eps = s->ek[sp] * (vx * vx + vy * vy + vz * vz);
-            s->wall_hits[sp][wall]++;
-            s->wall_esum[sp][wall] += eps;
-            int64_t b = (int64_t)(eps * ((double)p->eepf_bins / s->fedf_emax[sp]));
-            if (b >= 0 && b < p->eepf_bins) s->fedf[sp][(int64_t)wall * p->eepf_bins + b]++;
-          }
-          double ub = u01(r0[0]);
-          if (sp == 0) {
-            if (ub < p->reflection) {
-              /* elastic (specular) reflection */
-              x = (x < 0.0) ? -x : (L + L) - x;
-              vx = -vx;
-              if (x < 0.0 || x > L) {
-                alive = 0;
-                code |= 4;
-                s->counters[C_REFLECT_LOST]++;
-              } else {
-                code |= 2;
-                s->counters[C_E_REFLECTED]++;
-              }
-            } else {
-              alive = 0;
-              code |= 1;
-              s->counters[C_E_ABSORBED]++;
-            }
-          } else {
-            alive = 0;
-            s->counters[C_I_ABSORBED]++;
-            if (ub < p->gamma_see) {
-              /* ion-induced secondary electron, emitted from the hit wall
-               * with a half-Maxwellian velocity at see_temp_ev */
-              uint32_t r3[4];
-              draw(s, i, 1, 3, r3);
-              double n1, n2, n3, dummy;
-              box_muller(u01(r3[0]), u01(r3[1]), &n1, &n2);
-              box_muller(u01(r3[2]), u01(r3[3]), &n3, &dummy);
-              double xw = (x < 0.0) ? 0.0 : L;
-              double vxs = s->sig_se * fabs(n1);
-              if (x > L) vxs = -vxs;
-              plist_push(&se, xw, vxs, s->sig_se * n2, s->sig_se * n3);
-              code |= 3;
-              s->counters[C_SE_EMITTED]++;
-            } else {
-              code |= 1;
-            }
-          }
-          if (s->measuring && !alive) s->wall_abs[sp][wall]++;
-        }
-        /* (6) null-collision Monte Carlo */
-        int child = 0;
-        double cx = 0, cvx = 0, cvy = 0, cvz = 0;
-        if (alive && !(p->flags & F_NO_COLL) && u01(candidacy_word(s, i, sp)) < s->pcoll[sp]) {
-          double nu[3];
-          if (sp == 0) {
-            s->counters[C_E_CAND]++;
-            double v2 = vx * vx + vy * vy + vz * vz;
-            double speed = sqrt(v2);
-            if (table_lookup(s, 0, speed, nu) != 0) s->counters[C_BEYOND]++;
-            {
-              double r = u01(r0[2]) * s->numax[0];
-              uint32_t r1[4];
-              if (r < nu[0]) {
-                /* elastic: two-body kinematics, atom at rest, isotropic in
-                 * the centre-of-mass frame */
-                draw(s, i, 0, 1, r1);
-                double nx_, ny_, nz_;
-                if ((p->flags & F_ANISO) && speed > 0.0)
-                  deflect(vx / speed, vy / speed, vz / speed, s->ek_e * v2, u01(r1[0]), u01(r1[1]),
-                          &nx_, &ny_, &nz_);
-                else
-                  iso_dir(u01(r1[0]), u01(r1[1]), &nx_, &ny_, &nz_);
-                double g = s->mm_e * speed;
-                vx = s->mr_e * vx + g * nx_;
-                vy = s->mr_e * vy + g * ny_;
-                vz = s->mr_e * vz + g * nz_;
-                code |= 2 << 3;
-                s->counters[C_E_ELASTIC]++;
-              } else if (r < nu[1]) {
-                /* excitation: threshold energy lost, new direction isotropic */
-                draw(s, i, 0, 1, r1);
-                double eps = s->ek_e * v2 - p->exc_threshold_ev;
-                if (eps < 0.0) eps = 0.0;
-                double sp1 = sqrt(eps * s->ve_e);
-                double nx_, ny_, nz_;
-                iso_dir(u01(r1[0]), u01(r1[1]), &nx_, &ny_, &nz_);
-                vx = sp1 * nx_;
-                vy = sp1 * ny_;
-                vz = sp1 * nz_;
-                code |= 3 << 3;
-                s->counters[C_E_EXC]++;
-              } else if (r < nu[2]) {
-                /* ionization: the energy above threshold is shared
-                 * uniformly between the scattered and the ejected electron,
-                 * both isotropic; the new ion is thermal */
-                draw(s, i, 0, 1, r1);
-                uint32_t r2[4], r3[4];
-                draw(s, i, 0, 2, r2);
-                draw(s, i, 0, 3, r3);
-                double eps = s->ek_e * v2 - p->ion_threshold_ev;
-                if (eps < 0.0) eps = 0.0;
-                /* uniform sharing, or (variant) the Opal et al. form whose
-                 * cumulative distribution on [0, eps/2] is
-                 * atan(e / w) / atan(eps / (2 w)) */
-                double e_ej = (p->flags & F_OPAL) ? OPAL_W * tan(u01(r2[0]) * atan(eps / (2.0 * OPAL_W)))
-                                                  : u01(r2[0]) * eps;
-                double e_sc = eps - e_ej;
-                double s_sc = sqrt(e_sc * s->ve_e);
-                double s_ej = sqrt(e_ej * s->ve_e);
-                double ax, ay, az, bx, by, bz;
-                iso_dir(u01(r1[0]), u01(r1[1]), &ax, &ay, &az);
-                iso_dir(u01(r1[2]), u01(r1[3]), &bx, &by, &bz);
-                vx = s_sc * ax;
-                vy = s_sc * ay;
-                vz = s_sc * az;
-                child = 1;
-                cx = x;
-                cvx = s_ej * bx;
-                cvy = s_ej * by;
-                cvz = s_ej * bz;
-                double n1, n2, n3, dummy;
-                box_muller(u01(r3[0]), u01(r3[1]), &n1, &n2);
-                box_muller(u01(r3[2]), u01(r3[3]), &n3, &dummy);
-                plist_push(&ibirth, x, s->sig_g * n1, s->sig_g * n2, s->sig_g * n3);
-                code |= 4 << 3;
-                s->counters[C_E_ION]++;
-                if (s->measuring) s->ioniz_meas++;
-              } else {
-                code |= 1 << 3;
-              }
-            }
-          } else {
-            /* Ar+ on a thermal Ar atom drawn for the candidate */
-            s->counters[C_I_CAND]++;
-            uint32_t r1[4];
-            draw(s, i, 1, 1, r1);
-            double n1, n2, n3, dummy;
-            box_muller(u01(r1[0]), u01(r1[1]), &n1, &n2);
-            box_muller(u01(r1[2]), u01(r1[3]), &n3, &dummy);
-            double ax = s->sig_g * n1, ay = s->sig_g * n2, az = s->sig_g * n3;
-            double gx = vx - ax, gy = vy - ay, gz = vz - az;
-            double g = sqrt(gx * gx + gy * gy + gz * gz);
-            if (table_lookup(s, 1, g, nu) != 0) s->counters[C_BEYOND]++;
-            {
-              double r = u01(r0[2]) * s->numax[1];
-              if (r < nu[0]) {
-                /* isotropic elastic in the centre-of-mass frame (equal masses) */
-                uint32_t r2[4];
-                draw(s, i, 1, 2, r2);
-                double ux, uy, uz;
-                iso_dir(u01(r2[0]), u01(r2[1]), &ux, &uy, &uz);
-                double hg = 0.5 * g;
-                vx = 0.5 * (vx + ax) + hg * ux;
-                vy = 0.5 * (vy + ay) + hg * uy;
-                vz = 0.5 * (vz + az) + hg * uz;
-                code |= 2 << 3;
-                s->counters[C_I_ISO]++;
-              } else if (r < nu[1]) {
-                /* backward scattering = symmetric charge transfer: the ion
-                 * leaves with the atom's velocity */
-                vx = ax;
-                vy = ay;
-                vz = az;
-                code |= 3 << 3;
-                s->counters[C_I_BACK]++;
-              } else {
-                code |= 1 << 3;
-              }
-            }
-          }
-        }
-        if (p->flags & F_RECORD) s->codes[sp][i] = code;
-        if (alive) {
-          plist* out = (sp == 0) ? &eout : &iout;
-          plist_push(out, x, vx, vy, vz);
-          if (child) plist_push(out, cx, cvx, cvy, cvz);
-        }
+      const int64_t n = q->n;
+      int nrun = 1;
+#ifdef _OPENMP
+      nrun = omp_get_max_threads();
+      if ((int64_t)nrun > n) nrun = n > 0 ? (int)n : 1;
+#endif
+      ora_run* runs = (ora_run*)calloc((size_t)nrun, sizeof(ora_run));
+      for (int k = 0; k < nrun; k++) {
+        int64_t len = n * (k + 1) / nrun - n * k / nrun;
+        plist_init(&runs[k].out, 2 * len + 1);
+        plist_init(&runs[k].ibirth, len + 1);
+        plist_init(&runs[k].se, len + 1);
+        for (int w = 0; w < 2; w++)
+          runs[k].fedf[w] = (int64_t*)calloc((size_t)(2 * p->eepf_bins), sizeof(int64_t));
       }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static, 1)
+#endif
+      for (int k = 0; k < nrun; k++)
+        for (int64_t i = n * k / nrun; i < n * (k + 1) / nrun; i++) step_slot(s, sp, i, &runs[k]);
+      /* join the runs in slot order */
+      for (int k = 0; k < nrun; k++) {
+        ora_run* c = &runs[k];
+        plist_append((sp == 0) ? &eout : &iout, &c->out);
+        plist_append(&ibirth, &c->ibirth);
+        plist_append(&se, &c->se);
+        for (int m = 0; m < NCOUNT; m++) s->counters[m] += c->counters[m];
+        for (int a = 0; a < 2; a++)
+          for (int w = 0; w < 2; w++) {
+            s->wall_hits[a][w] += c->wall_hits[a][w];
+            s->wall_abs[a][w] += c->wall_abs[a][w];
+            s->wall_esum[a][w] += c->wall_esum[a][w];
+          }
+        for (int w = 0; w < 2; w++)
+          for (int64_t b = 0; b < 2 * (int64_t)p->eepf_bins; b++) s->fedf[w][b] += c->fedf[w][b];
+        s->ioniz_meas += c->ioniz_meas;
+        if (c->err && !s->err) s->err = c->err;
+        plist_free(&c->out);
+        plist_free(&c->ibirth);
+        plist_free(&c->se);
+        free(c->fedf[0]);
+        free(c->fedf[1]);
+      }
+      free(runs);
     }
 
     /* rebuild: e = [survivors with ionization electrons after their parent]
