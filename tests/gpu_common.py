@@ -49,3 +49,18 @@ def pair(params, xs, init, step=0, fixed_E=None):
         gpu.set_state(sp, *init[sp], step=step)
         ora.set_state(sp, *init[sp], step=step)
     return gpu, ora
+
+
+def near_wall_state(n, L, vscale, reach, seed, species, frac=0.05):
+    """Uniform particles with Gaussian velocities; a fraction sits within
+    `reach` of a wall and moves towards it."""
+    rng = np.random.default_rng([seed, species, 5])
+    x = rng.uniform(0, L, n)
+    v = rng.normal(0, vscale, (3, n))
+    k = int(frac * n)
+    idx = rng.choice(n, size=k, replace=False)
+    side = rng.integers(0, 2, k)
+    d = rng.uniform(0, reach, k)
+    x[idx] = np.where(side == 0, d, L - d)
+    v[0, idx] = np.where(side == 0, -1, 1) * np.abs(v[0, idx])
+    return (x, v[0].copy(), v[1].copy(), v[2].copy())

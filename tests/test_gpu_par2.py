@@ -1,0 +1,84 @@
+"""Run-level statistical parity of the GPU path with the oracle (Sec. 3.1:
+time-averaged density profiles of both species, the electron mean-energy
+profile and the EEPF at mid-gap), 8 GPU seeds (1-8) against 8 oracle seeds
+(101-108), by the procedure of tests/par2.py: per node or bin the Welch
+difference within the 3-sigma-equivalent Student-t bound on at least 99 %
+of them, and per quantity Hotelling's T^2 over coarse bands below its 99.9th
+percentile.
+
+Two discharges: the small case for its full 10 RF cycles (2 cycles before
+measuring, 8 measured), and one shaped like the production case (512 cells,
+N_t = 4000, 50 Pa, 300 V, gamma 0.1, R 0) scaled to 20k particles per
+species with the weight rescaled, for 2 RF cycles (1 + 1). The oracle runs
+in worker processes while the GPU runs its ensemble as one batch."""
+import numpy as np
+import pytest
+
+import par2
+from gpu_common import need_gpu
+from pic_inputs import state, workloads, xsec
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _gpu_ensemble(w, seeds, warm, measured):
+    import torch
+
+    from paper_2109_04469_amd import Batch, Discharge
+
+    xs = xsec.argon_synthetic()
+    stream = torch.cuda.Stream()
+    ds = []
+    for s in seeds:
+        d = Discharge(dict(w["params"], seed=s), xs, stream=stream)
+        init = state.initial_state(w, seed=s)
+        for sp in (0, 1):
+            d.set_state(sp, *init[sp], step=0)
+        ds.append(d)
+    b = Batch(ds)
+    b.step(warm)
+    for d in ds:
+        assert d.sync() == 0
+        d.measure(True)
+        d.moments(reset=True)
+    b.step(measured)
+    out = []
+    for d in ds:
+        assert d.sync() == 0
+        m = d.moments()
+        assert m["steps"] == measured
+        out.append(dict(m, ne=d.count(0), ni=d.count(1)))
+    b.close()
+    return out
+
+
+CASES = {
+    "c1_full_10_cycles": (lambda: workloads.get("c1_small"), 2000, 8000),
+    "c2_shaped_20k_2_cycles": (lambda: workloads.scaled(workloads.get("c2_production"), 20_000),
+                               4000, 4000),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_ensemble_statistics_match_oracle(case):
+    mk, warm, measured = CASES[case]
+    w = mk()
+    print(f"[par2] {case}: oracle seeds 101-108 in workers, GPU seeds 1-8", flush=True)
+    pending = par2.oracle_ensemble_async(w, range(101, 109), warm, measured)
+    g = _gpu_ensemble(w, range(1, 9), warm, measured)
+    o = pending.get(timeout=600)
+    rep = par2.compare(g, o)
+    print(f"[par2] {case}: node fraction {rep['node_fraction']:.4f}, "
+          + ", ".join(f"{k} F {v['hotelling_f']:.2f} < {v['f_limit']:.2f}"
+                      for k, v in rep.items() if isinstance(v, dict)), flush=True)
+    assert rep["ok"], rep
+    # the same numbers of particles are alive on average (a loose sanity
+    # bound on top of the statistics above)
+    ne_g = np.mean([r["ne"] for r in g])
+    ne_o = np.mean([r["ne"] for r in o])
+    assert abs(ne_g / ne_o - 1) < 0.2

@@ -8,7 +8,7 @@ velocities (only the scattering transcendentals may differ by ulps).
 import numpy as np
 import pytest
 
-from gpu_common import assert_state_close, assert_state_equal, need_gpu, pair
+from gpu_common import assert_state_close, assert_state_equal, near_wall_state, need_gpu, pair
 from helpers import FIXED_E, NO_COLL, RECORD, THOMAS, ME, MAR, QE, params
 from pic_inputs import state, workloads, xsec
 
@@ -108,21 +108,6 @@ def test_field_exact_solver_within_rounding(n_cells):
     assert np.max(np.abs(fg["E"] - fo["E"])) < 8 * nx * eps * Es
 
 
-def _near_wall_state(n, L, vscale, reach, seed, species, frac=0.05):
-    """Uniform particles with Gaussian velocities; a fraction sits within
-    `reach` of a wall and moves towards it."""
-    rng = np.random.default_rng([seed, species, 5])
-    x = rng.uniform(0, L, n)
-    v = rng.normal(0, vscale, (3, n))
-    k = int(frac * n)
-    idx = rng.choice(n, size=k, replace=False)
-    side = rng.integers(0, 2, k)
-    d = rng.uniform(0, reach, k)
-    x[idx] = np.where(side == 0, d, L - d)
-    v[0, idx] = np.where(side == 0, -1, 1) * np.abs(v[0, idx])
-    return (x, v[0].copy(), v[1].copy(), v[2].copy())
-
-
 def _single_step_case(n, seed, step, subcycle, flags, R=0.3, gamma=0.25, n_cells=128):
     p = params(n_cells=n_cells, reflection=R, gamma_see=gamma, ion_subcycle=subcycle,
                flags=flags | RECORD, capacity=(3 * n + 64, 3 * n + 64), sort_interval=0,
@@ -132,8 +117,8 @@ def _single_step_case(n, seed, step, subcycle, flags, R=0.3, gamma=0.25, n_cells
     dt = 1.0 / (p["rf_freq_hz"] * p["steps_per_cycle"])
     ve = _vth(3.0, ME)
     vi = _vth(50.0, MAR)
-    e = _near_wall_state(n, L, ve, ve * dt, seed, 0)
-    i = _near_wall_state(n + 17, L, vi, vi * dt * subcycle, seed, 1)
+    e = near_wall_state(n, L, ve, ve * dt, seed, 0)
+    i = near_wall_state(n + 17, L, vi, vi * dt * subcycle, seed, 1)
     rng = np.random.default_rng(seed + 1)
     E = rng.normal(0, 3e4, n_cells + 1) if flags & FIXED_E else None
     return p, xs, {0: e, 1: i}, E, L, ve, vi
