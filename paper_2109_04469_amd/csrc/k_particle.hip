@@ -16,7 +16,9 @@
 //             kTile slots,
 //             and deposits the new positions (and those of births) into LDS
 //             fixed-point histograms flushed with integer atomics.
-//   k_emit    takes a contiguous run of tiles per workgroup, forms its prefix
+//   k_emit    takes a contiguous run of tiles per workgroup for electrons and
+//             tiles blockIdx.x, blockIdx.x + gridDim.x, ... for ions (carrying
+//             the prefix over the tiles in between), forms its prefix
 //             from the per-tile totals, scans the codes inside each tile and
 //             writes every output to its compacted slot: it re-reads the
 //             particle and repeats the push bit for bit (same arithmetic, no
@@ -56,16 +58,16 @@ __device__ __forceinline__ void stage_field(double* sE, const double* E, int nx)
     }
   }
 }
-// Code bit used between the two kernels only: an Ar+ collision candidate
-// whose process (which needs a thermal atom velocity) is chosen in k_emit.
-// k_emit replaces it with the process bits, so a code read by the caller has
-// bit 6 clear.
+// Code bit used between the kernels of a pass only: an Ar+ collision
+// candidate whose process (which needs a thermal atom velocity) is chosen by
+// rare_slot in k_rare / k_tail, which replaces it with the process bits, so a
+// code read by the caller has bit 6 clear.
 constexpr uint32_t kIonPending = 0x40u;
 
 struct Outcome {
   uint32_t own;    // output slots of this species: 0, 1 or 2
   uint32_t birth;  // births of the other species: 0 or 1
-  bool rare;       // needs draws in k_emit
+  bool rare;       // queued: needs draws in k_rare / k_tail
 };
 
 // What a decision code implies for the outputs. Slots carried without a

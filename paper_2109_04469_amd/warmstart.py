@@ -329,16 +329,44 @@ def evaluate(data, warm_cycles=600, deltas=(0.05, 0.10), train_steps=3000, seed=
     for delta in deltas:
         cold = [cycles_to(dist_cold[:, k], delta) for k in range(len(test))]
         wrm = [cycles_to(dist_warm[:, k], delta) for k in range(len(test))]
-        both = [(c, w_) for c, w_ in zip(cold, wrm) if c is not None and w_ is not None]
-        res[f"delta_{delta:g}"] = {
-            "cold_cycles": cold, "warm_cycles": wrm,
-            "mean_cold": float(np.mean([c for c, _ in both])) if both else None,
-            "mean_warm": float(np.mean([w_ for _, w_ in both])) if both else None,
-            "speedup": (float(np.mean([c for c, _ in both]) / np.mean([w_ for _, w_ in both]))
-                        if both else None),
-            "converged_cold": sum(c is not None for c in cold),
-            "converged_warm": sum(w_ is not None for w_ in wrm),
-        }
+        res[f"delta_{delta:g}"] = compare_cycles(cold, wrm, int(data["cycles"]), warm_cycles)
+    return res
+
+
+def compare_cycles(cold, warm, cold_cap, warm_cap):
+    """Cycles to convergence of the same discharges started cold and warm. A
+    run that never converged counts at the cycles it ran (cold_cap,
+    warm_cap), a lower bound on what it needs, so no run drops out of the
+    means and medians; the counts of such runs are reported beside them."""
+    c = np.array([x if x is not None else cold_cap for x in cold], dtype=float)
+    w = np.array([x if x is not None else warm_cap for x in warm], dtype=float)
+    out = {"cold_cycles": cold, "warm_cycles": warm,
+           "converged_cold": sum(x is not None for x in cold),
+           "converged_warm": sum(x is not None for x in warm),
+           "unconverged_counted_at": {"cold": cold_cap, "warm": warm_cap}}
+    if len(c):
+        out.update({"mean_cold": float(c.mean()), "mean_warm": float(w.mean()),
+                    "median_cold": float(np.median(c)), "median_warm": float(np.median(w)),
+                    "speedup_mean": float(c.mean() / w.mean()),
+                    "speedup_median": float(np.median(c) / np.median(w)),
+                    "warm_faster": int((w < c).sum()), "warm_slower": int((w > c).sum())})
+    return out
+
+
+def study(n_train, n_test, cycles, avg_windows, warm_cycles, deltas=(0.05, 0.10),
+          train_steps=3000, seed=0):
+    """The whole study at a chosen size: cold runs of n_train + n_test
+    discharges (their converged averages train the network and judge the
+    held-out runs), then the held-out discharges started from the network's
+    predictions. Returns evaluate()'s result with the cold-run time."""
+    t0 = time.time()
+    data = generate(n_train, n_test, cycles, avg_windows, seed)
+    t_cold = time.time() - t0
+    res = evaluate(data, warm_cycles=warm_cycles, deltas=deltas, train_steps=train_steps,
+                   seed=seed)
+    res["cold_run_seconds"] = t_cold
+    return res
+
     return res
 
 

@@ -15,23 +15,31 @@ from .xsec import E_CHARGE, M_ARGON, M_ELECTRON
 MASS = (M_ELECTRON, M_ARGON)
 
 
-def maxwellian_uniform(n, gap_m, temp_ev, species, seed):
+def maxwellian_uniform(n, gap_m, temp_ev, species, seed, ordered=False):
     """n particles uniform in (0, L) with Maxwellian velocities; returns
-    float64 arrays (x, vx, vy, vz)."""
+    float64 arrays (x, vx, vy, vz). ordered: the positions are listed in
+    increasing order (the same draws, relabelled), the slot order a cell
+    sort of the uniform load would give."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(species), 7])))
     x = rng.uniform(0.0, gap_m, size=n)
+    if ordered:
+        x = np.sort(x, kind="stable")
     sig = np.sqrt(temp_ev * E_CHARGE / MASS[species])
     v = rng.normal(0.0, sig, size=(3, n))
     return (np.ascontiguousarray(x), np.ascontiguousarray(v[0]),
             np.ascontiguousarray(v[1]), np.ascontiguousarray(v[2]))
 
 
-def initial_state(workload, seed=None):
-    """Both species of a named workload: {species: (x, vx, vy, vz)}."""
+def initial_state(workload, seed=None, ordered=None):
+    """Both species of a named workload: {species: (x, vx, vy, vz)}.
+    ordered (default: the workload's "ordered_load"): positions listed in
+    increasing order."""
     p = workload["params"]
     s = p["seed"] if seed is None else seed
+    o = workload.get("ordered_load", False) if ordered is None else ordered
     return {
-        sp: maxwellian_uniform(workload["n_init"][sp], p["gap_m"], workload["t_init_ev"][sp], sp, s)
+        sp: maxwellian_uniform(workload["n_init"][sp], p["gap_m"], workload["t_init_ev"][sp], sp, s,
+                               ordered=o)
         for sp in (0, 1)
     }
 

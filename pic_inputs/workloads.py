@@ -75,13 +75,15 @@ C2 = dict(
 # ions sub-cycled x10, 100 RF cycles. Particles move a few cells per 100
 # steps here; a cell sort every 200 steps gave the shortest mean step
 # (measured over 25 to 1000: the sort's cost against the deposit and field
-# locality lost between sorts).
+# locality lost between sorts). The initial load is listed in increasing
+# position, the order the periodic cell sort keeps the particles in, so a
+# short run from the load sees the layout of the steady run.
 C3 = dict(
     name="c3_large_lowp",
     params=_mk(gap_m=0.067, n_cells=2048, steps_per_cycle=8000, rf_voltage_v=500.0,
                pressure_pa=2.0, weight=8375.0, reflection=0.5, gamma_see=0.2,
                capacity=(16_000_000, 16_000_000), ion_subcycle=10, sort_interval=200, run=3),
-    n_init=(4_000_000, 4_000_000), t_init_ev=(2.0, 0.03), cycles=100,
+    n_init=(4_000_000, 4_000_000), t_init_ev=(2.0, 0.03), cycles=100, ordered_load=True,
 )
 
 WORKLOADS = {w["name"]: w for w in (C1, C2, C3)}
