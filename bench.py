@@ -7,7 +7,7 @@ kernel, the sub-cycled ion kernel on its steps and the periodic cell sort.
 The default workload is the large low-pressure discharge: 6.7 cm gap, 2048
 cells, dt = T_RF/8000, 2 Pa, 500 V, gamma = 0.2, R = 0.5, 4M electrons + 4M
 Ar+ in FP64, ions sub-cycled x10, synthetic argon-shaped cross sections,
-starting from a uniform Maxwellian plasma. After `--warmup` steps (default
+starting from a uniform Maxwellian plasma listed in position order. After `--warmup` steps (default
 two RF cycles) `--steps` steps (default one RF cycle) are timed with inputs
 resident in HBM.
 
@@ -23,15 +23,21 @@ of the same length right after the timed one (event records slow a step by a
 few percent, so the timed window itself has none). copy_ref is the
 library's plain streaming copy on 2 x 256 MiB, the achievable-bandwidth
 reference on the same GPU.
-cpu_baseline: the CPU oracle (single thread) on a bounded sample of the same
-workload.
+sort: the periodic cell sort's cost per sort and amortised per step (the
+timed window may hold no sort), and the throughput with it included.
+cpu_baseline: the CPU oracle (single thread, and the OpenMP build of the same
+source on all host cores) on a bounded sample of the same workload, with the
+host's CPU model and core count.
+c1_full: the small discharge for its full 10 RF cycles on the GPU and on the
+oracle.
 sweep: the batched-sweep workload (64 seeded independent discharges of
 uneven size), advanced one discharge after the other, on one stream each,
 and as one batch with one launch per pass for all; throughputs, speedups
 over the one-after-the-other run, and whether all three agree bitwise.
-warm_start (with --warm-start only, about 10 GPU-minutes): RF cycles to
-convergence of 16 held-out discharges started from the network's predicted
-profiles vs from a uniform plasma (paper_2109_04469_amd.warmstart).
+warm_start (default: a reduced study, about 2 GPU-minutes; --warm-start full
+for the 10-minute one): RF cycles to convergence of held-out discharges
+started from the network's predicted profiles vs from a uniform plasma
+(paper_2109_04469_amd.warmstart).
 """
 import argparse
 import json
@@ -47,9 +53,13 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE_STEP = 64
 # HBM bytes the electron pass moves per electron particle-step, read with
 # rocprofv3 FETCH_SIZE (x2, the factor a plain copy of known size gives)
-# and WRITE_SIZE (x1) at c3; to be re-measured whenever the pass's kernels
-# change (None when not measured for the current kernels)
+# and WRITE_SIZE (x1) at c3; a constant taken from the profile named below,
+# to be re-measured whenever the pass's kernels change (None when not
+# measured for the current kernels)
 PASS_TRAFFIC_BYTES_PER_PARTICLE = 60.15
+PASS_TRAFFIC_SOURCE = ("constant per electron particle-step from "
+                       "profiles/particle_pass_c3_large_lowp_hbm_traffic.md (rocprofv3 FETCH_SIZE x2 + "
+                       "WRITE_SIZE over 20 steps after two RF cycles), times this window's particles")
 
 DESCRIPTIONS = {
     "c3_large_lowp": ("gap 6.7 cm, 2048 cells, dt=T_RF/8000, 13.56 MHz, 500 V, 2 Pa, gamma 0.2, R 0.5, "
@@ -61,11 +71,24 @@ DESCRIPTIONS = {
 }
 
 
-def cpu_baseline(workload, init, xs, nsteps):
+def host_cpu():
+    """Host CPU model and the cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": len(os.sched_getaffinity(0)), "os_cpu_count": os.cpu_count()}
+
+
+def _oracle_run(workload, init, xs, nsteps, openmp):
     import oracle
 
-    p = dict(workload["params"])
-    o = oracle.Oracle(p, xs)
+    o = oracle.Oracle(dict(workload["params"]), xs, openmp=openmp)
     for sp in (0, 1):
         o.set_state(sp, *init[sp], step=0)
     c0 = o.counters()
@@ -74,13 +97,70 @@ def cpu_baseline(workload, init, xs, nsteps):
     t1 = time.perf_counter()
     c1 = o.counters()
     ps = int((c1[1] - c0[1]) + (c1[2] - c0[2]))
+    return ps, t1 - t0, st
+
+
+def cpu_baseline(workload, init, xs, nsteps):
+    """The oracle on this host: the plain single-threaded build (the
+    checker) and the OpenMP build of the same source on all the host's
+    cores, both on the first nsteps steps of the workload."""
+    import oracle
+
+    ps, sec, st = _oracle_run(workload, init, xs, nsteps, False)
+    ps_m, sec_m, st_m = _oracle_run(workload, init, xs, nsteps, True)
+    cpu = host_cpu()
     return {
-        "value": ps / (t1 - t0),
+        "value": ps / sec,
         "unit": "particle-steps/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"first {nsteps} steps of {workload['name']} from its synthetic initial state "
-                  f"({ps} particle-steps, {t1 - t0:.1f} s, status {st})",
+                  f"({ps} particle-steps, {sec:.1f} s, status {st})",
+        "openmp": {"value": ps_m / sec_m, "unit": "particle-steps/s",
+                   "cores": oracle.threads(openmp=True), "seconds": sec_m, "status": st_m,
+                   "note": "same oracle source built with -fopenmp: each pass split into one "
+                           "slot-ordered run per thread (bit-identical results)"},
+        "host": cpu,
+    }
+
+
+def c1_full(torch, log):
+    """The small discharge in full (10 RF cycles, 10k + 10k particles) on the
+    GPU and on the oracle (plain and OpenMP builds), from the same state."""
+    from paper_2109_04469_amd import Discharge
+    from pic_inputs import state, workloads, xsec
+
+    w = workloads.get("c1_small")
+    p = dict(w["params"])
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w)
+    nsteps = w["cycles"] * p["steps_per_cycle"]
+    d = Discharge(p, xs, "cuda:0")
+    for sp in (0, 1):
+        d.set_state(sp, *init[sp], step=0)
+    torch.cuda.synchronize()
+    c0 = d.counters()
+    t0 = time.perf_counter()
+    d.step(nsteps)
+    st = d.sync()
+    t1 = time.perf_counter()
+    assert st == 0, f"c1 run failed: status {st}"
+    c1 = d.counters()
+    ps = int((c1[1] - c0[1]) + (c1[2] - c0[2]))
+    log(f"[bench] c1 in full: GPU {t1 - t0:.2f} s; oracle (plain, then OpenMP)")
+    ops, osec, ost = _oracle_run(w, init, xs, nsteps, False)
+    mps, msec, mst = _oracle_run(w, init, xs, nsteps, True)
+    import oracle
+
+    return {
+        "workload": f"c1_small in full: {DESCRIPTIONS['c1_small']}, {w['cycles']} RF cycles "
+                    f"({nsteps} steps) from the synthetic initial state",
+        "unit": "particle-steps/s",
+        "gpu": {"value": ps / (t1 - t0), "seconds": t1 - t0, "particle_steps": ps},
+        "oracle_1_core": {"value": ops / osec, "seconds": osec, "particle_steps": ops, "status": ost},
+        "oracle_openmp": {"value": mps / msec, "seconds": msec, "particle_steps": mps, "status": mst,
+                          "cores": oracle.threads(openmp=True)},
+        "note": "c1 is launch- and latency-bound on the GPU (20k particles); it is the parity case",
     }
 
 
@@ -205,9 +285,11 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched-sweep workload")
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the batched-sweep workload and print its JSON object")
-    ap.add_argument("--warm-start", action="store_true",
-                    help="also run the warm-start study (about 10 GPU-minutes: 112 cold runs of "
-                         "2000 RF cycles, training, 16 warm runs of 1500 cycles)")
+    ap.add_argument("--warm-start", choices=("reduced", "full", "none"), default="reduced",
+                    help="warm-start study: reduced (default, about 2 GPU-minutes: 28 cold runs of "
+                         "1000 RF cycles, training on 24, 4 warm runs of 400 cycles), full (about 10 "
+                         "GPU-minutes: 112 cold runs of 2000 cycles, 16 warm runs of 1500) or none")
+    ap.add_argument("--no-c1", action="store_true", help="skip the small discharge in full")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs one discharge on one GPU; --gpus {args.gpus} is not supported "
@@ -270,6 +352,7 @@ def main():
 
     roof = None
     kernels = None
+    sort_block = None
     if not args.no_timing:
         # the same number of steps again with HIP events around the field
         # kernel, each species' particle pass and each sort (event records
@@ -293,6 +376,27 @@ def main():
         kernels.update({k: {"launches": v[1], "us_per_launch": 1e3 * v[0] / v[1],
                             "note": "events around each kernel"}
                         for k, v in tk.items() if v[1] and k.split("_")[0] in ("e", "i")})
+        # the periodic cell sort: when the windows above hold none, step on
+        # to the next sort with events around it, so its cost per step can
+        # be stated (it is part of every step in the mean over a sort
+        # interval)
+        si = p["sort_interval"]
+        sort_ms = tm.get("sort", (0.0, 0))
+        sort_ms = (sort_ms[0] + tk.get("sort", (0.0, 0))[0], sort_ms[1] + tk.get("sort", (0.0, 0))[1])
+        if si > 0 and sort_ms[1] == 0:
+            d.timing(1)
+            d.get_timing(reset=True)
+            d.step(si - d.step_index % si)
+            assert d.sync() == 0
+            ts = d.get_timing(reset=True)
+            d.timing(0)
+            sort_ms = ts.get("sort", (0.0, 0))
+        if si > 0 and sort_ms[1]:
+            us_sort = 1e3 * sort_ms[0] / sort_ms[1]
+            sort_block = {"interval_steps": si, "us_per_sort": us_sort,
+                          "sorts_timed": sort_ms[1], "us_per_step_amortised": us_sort / si,
+                          "value_with_sort_amortised": (pe + pi) / (elapsed + steps * us_sort / si * 1e-6),
+                          "note": "both species' stable cell sorts, HIP events around them"}
         ems, en = tm["electron"]
         if en:
             avg_s = ems / en * 1e-3
@@ -302,7 +406,7 @@ def main():
                        if PASS_TRAFFIC_BYTES_PER_PARTICLE is not None else None)
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                    "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
+                    "traffic_unit": "HBM bytes per launch", "traffic_source": PASS_TRAFFIC_SOURCE,
                     "kernel": ("electron particle pass: k_decide<0> + k_emit<0> + k_tail<0> "
                                "(its queued slots, overlapped with the next step's field); "
                                "k_rare<0> instead of k_tail on ion steps"),
@@ -331,6 +435,7 @@ def main():
         },
         "roofline": roof,
         "kernels": kernels,
+        "sort": sort_block,
         "cpu_baseline": None,
         "copy_ref": copy_reference(torch),
     }
@@ -339,24 +444,31 @@ def main():
         del d
         torch.cuda.empty_cache()
         out["sweep"] = sweep_measurement(torch, args.sweep_steps, log=log)
-    out["warm_start"] = {
-        "not_run": "the warm-start study takes about 10 GPU-minutes; run bench.py --warm-start "
-                   "(results of a previous run in profiles/warm_start_study.md)"}
-    if args.warm_start:
+    out["warm_start"] = None
+    if args.warm_start != "none":
         from paper_2109_04469_amd import warmstart
 
-        log("[bench] warm-start study: cold runs")
-        data = warmstart.generate()
-        log("[bench] warm-start study: training and warm runs")
-        res = warmstart.evaluate(data, warm_cycles=1500)
+        size = (dict(n_train=24, n_test=4, cycles=1000, avg_windows=20, warm_cycles=400,
+                     train_steps=2000, seed=3) if args.warm_start == "reduced" else
+                dict(n_train=96, n_test=16, cycles=2000, avg_windows=20, warm_cycles=1500,
+                     train_steps=3000, seed=0))
+        log(f"[bench] warm-start study ({args.warm_start}): cold runs, training, warm runs")
+        res = warmstart.study(**size)
         out["warm_start"] = {
-            "workload": "warm-start family (seed 0): 96 training + 16 held-out discharges",
+            "workload": (f"warm-start family (seed {size['seed']}): {size['n_train']} training + "
+                         f"{size['n_test']} held-out discharges, cold runs of {size['cycles']} RF "
+                         f"cycles (reference: mean of the last {size['avg_windows'] * 10}), warm runs "
+                         f"of {size['warm_cycles']}"),
             "metric": "RF cycles until the 10-cycle-averaged ion density stays within delta of the "
-                      "converged cold-run reference",
+                      "cold-run reference (runs that never converge counted at the cycles they ran)",
             "delta_0.1": res["delta_0.1"], "delta_0.05": res["delta_0.05"],
             "prediction_rel_l2_n_i": res["prediction_rel_l2_n_i"],
+            "initial_rel_l2_n_i": res["initial_rel_l2_n_i"],
+            "cold_run_seconds": res["cold_run_seconds"],
             "train_seconds": res["train_seconds"], "warm_run_seconds": res["warm_run_seconds"],
         }
+    if not args.no_c1:
+        out["c1_full"] = c1_full(torch, log)
     if not args.no_cpu:
         log(f"[bench] cpu baseline: oracle, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(w, init, xs, args.cpu_steps)
