@@ -286,9 +286,9 @@ def main():
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the batched-sweep workload and print its JSON object")
     ap.add_argument("--warm-start", choices=("reduced", "full", "none"), default="reduced",
-                    help="warm-start study: reduced (default, about 2 GPU-minutes: 28 cold runs of "
-                         "1000 RF cycles, training on 24, 4 warm runs of 400 cycles), full (about 10 "
-                         "GPU-minutes: 112 cold runs of 2000 cycles, 16 warm runs of 1500) or none")
+                    help="warm-start study: reduced (default, about 2 GPU-minutes: 46 cold runs of "
+                         "1000 RF cycles, training on 40, 6 warm runs of 1000 cycles), full (about 10 "
+                         "GPU-minutes: 112 cold runs of 2000 cycles, 16 warm runs of 2000) or none")
     ap.add_argument("--no-c1", action="store_true", help="skip the small discharge in full")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -448,10 +448,7 @@ def main():
     if args.warm_start != "none":
         from paper_2109_04469_amd import warmstart
 
-        size = (dict(n_train=24, n_test=4, cycles=1000, avg_windows=20, warm_cycles=400,
-                     train_steps=2000, seed=3) if args.warm_start == "reduced" else
-                dict(n_train=96, n_test=16, cycles=2000, avg_windows=20, warm_cycles=1500,
-                     train_steps=3000, seed=0))
+        size = warmstart.REDUCED_STUDY if args.warm_start == "reduced" else warmstart.FULL_STUDY
         log(f"[bench] warm-start study ({args.warm_start}): cold runs, training, warm runs")
         res = warmstart.study(**size)
         out["warm_start"] = {

@@ -336,21 +336,33 @@ def evaluate(data, warm_cycles=600, deltas=(0.05, 0.10), train_steps=3000, seed=
 def compare_cycles(cold, warm, cold_cap, warm_cap):
     """Cycles to convergence of the same discharges started cold and warm. A
     run that never converged counts at the cycles it ran (cold_cap,
-    warm_cap), a lower bound on what it needs, so no run drops out of the
-    means and medians; the counts of such runs are reported beside them."""
+    warm_cap: a lower bound on what it needs, so runs should be equally
+    long for a fair mean), and no run drops out of the means and medians.
+    A warm run is faster than its cold twin only if it converged first; one
+    that did not converge is never counted as faster."""
     c = np.array([x if x is not None else cold_cap for x in cold], dtype=float)
     w = np.array([x if x is not None else warm_cap for x in warm], dtype=float)
+    faster = sum(1 for a, b in zip(cold, warm) if b is not None and (a is None or b < a))
+    slower = sum(1 for a, b in zip(cold, warm) if a is not None and (b is None or b > a))
     out = {"cold_cycles": cold, "warm_cycles": warm,
            "converged_cold": sum(x is not None for x in cold),
            "converged_warm": sum(x is not None for x in warm),
-           "unconverged_counted_at": {"cold": cold_cap, "warm": warm_cap}}
+           "unconverged_counted_at": {"cold": cold_cap, "warm": warm_cap},
+           "warm_faster": faster, "warm_slower": slower}
     if len(c):
         out.update({"mean_cold": float(c.mean()), "mean_warm": float(w.mean()),
                     "median_cold": float(np.median(c)), "median_warm": float(np.median(w)),
                     "speedup_mean": float(c.mean() / w.mean()),
-                    "speedup_median": float(np.median(c) / np.median(w)),
-                    "warm_faster": int((w < c).sum()), "warm_slower": int((w > c).sum())})
+                    "speedup_median": float(np.median(c) / np.median(w))})
     return out
+
+
+# The study at the size a test or a benchmark line can afford (about two
+# GPU-minutes) and at the size of the full study.
+REDUCED_STUDY = dict(n_train=40, n_test=6, cycles=1000, avg_windows=20, warm_cycles=1000,
+                     train_steps=2000, seed=3)
+FULL_STUDY = dict(n_train=96, n_test=16, cycles=2000, avg_windows=20, warm_cycles=2000,
+                  train_steps=3000, seed=0)
 
 
 def study(n_train, n_test, cycles, avg_windows, warm_cycles, deltas=(0.05, 0.10),

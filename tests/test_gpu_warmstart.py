@@ -189,27 +189,27 @@ def test_run_to_convergence_driver():
 
 
 def test_warm_start_reaches_the_reference_sooner_than_cold():
-    # What the trained network gains, at toy size: 28 discharges of the
+    # What the trained network gains, at reduced size: 46 discharges of the
     # family (seed 3) run cold for 1000 RF cycles as one batch; the network
-    # is trained on the references (mean of cycles 800-1000) of 24 of them
-    # and the other 4 are loaded from its predictions and run 400 cycles.
-    # Convergence to delta = 10 % (ion density within delta of the reference
-    # and staying within 2 delta) must come sooner from the predicted
-    # profiles than from the uniform plasma: fewer RF cycles on average and
-    # for most held-out discharges, runs that never converge counted at the
-    # cycles they ran.
+    # is trained on the references (mean of cycles 800-1000) of 40 of them
+    # and the other 6 are loaded from its predictions and run for the same
+    # 1000 cycles. Convergence to delta = 10 % (ion density within delta of
+    # the reference and staying within 2 delta) must come sooner from the
+    # predicted profiles than from the uniform plasma: fewer RF cycles on
+    # average (runs that never converge counted at the 1000 cycles they ran)
+    # and for more of the held-out discharges than not (a warm run that
+    # never converges is never counted as faster).
     from paper_2109_04469_amd import warmstart
 
-    res = warmstart.study(n_train=24, n_test=4, cycles=1000, avg_windows=20, warm_cycles=400,
-                          deltas=(0.1,), train_steps=2000, seed=3)
+    res = warmstart.study(**warmstart.REDUCED_STUDY)
     r = res["delta_0.1"]
     print(f"[warm] cold {r['cold_cycles']} warm {r['warm_cycles']} "
           f"prediction error {np.round(res['prediction_rel_l2_n_i'], 3)} "
           f"start cold {np.round(res['initial_rel_l2_n_i']['cold'], 3)} "
           f"warm {np.round(res['initial_rel_l2_n_i']['warm'], 3)} "
           f"({res['cold_run_seconds']:.0f} s cold, {res['warm_run_seconds']:.0f} s warm)", flush=True)
-    assert res["n_test"] == 4 and all(res["warm_loaded"])
+    assert res["n_test"] == 6 and all(res["warm_loaded"])
     # the predicted start is closer to the converged profile than the cold one
     assert np.median(res["initial_rel_l2_n_i"]["warm"]) < np.median(res["initial_rel_l2_n_i"]["cold"])
     assert r["mean_warm"] < r["mean_cold"]
-    assert r["warm_faster"] >= 3
+    assert r["warm_faster"] > r["warm_slower"]
