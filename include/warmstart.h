@@ -86,6 +86,26 @@ int pic_mlp_train_step(pic_mlp* m, const float* x, const float* target, int batc
 /* Synchronises the stream and releases the host metadata. */
 void pic_mlp_free(pic_mlp* m);
 
+/* ---- forward pass for callers that cannot allocate ------------------------
+ * For callers that cannot allocate device memory or hold a workspace (code
+ * under HIP graph capture, tight serving loops predicting start profiles,
+ * harnesses that forbid allocation): y = network(x) for the parameter
+ * vector `params` of a network of the given shape (the layout of
+ * pic_mlp_set_params), the same arithmetic and kernels as pic_mlp_forward.
+ * params, x, y: DEVICE arrays of the current device (x [batch x n_in],
+ * y [batch x n_out], row-major), owned by the caller. The BF16 weight
+ * copies and the hidden activations live in a fixed device array of
+ * 8 MiB in the library (one per GPU, kept until the process ends); a call
+ * needs 2 * (number of weights) + 3 * batch * width * 4 bytes of it, each
+ * part rounded up to 256 bytes, and returns PIC_EINVAL beyond that (the
+ * 6 -> 4 x 256 -> 512 network takes batches up to 2516) or for bad shapes.
+ * No device memory is allocated and nothing needs clearing between calls.
+ * Calls on one GPU share the array: calls that overlap in time on one GPU
+ * (other streams or host threads) race and must be serialised by the
+ * caller. Asynchronous on `stream`; PIC_EHIP if a launch fails. */
+int pic_mlp_forward_static(int n_in, int width, int depth, int n_out, const float* params,
+                           const float* x, int batch, float* y, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

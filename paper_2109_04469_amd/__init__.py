@@ -12,7 +12,7 @@ from .capi import PicError  # noqa: F401
 def __getattr__(name):
     # torch is imported lazily so that the C ABI can be inspected without it
     if name in ("Discharge", "Batch", "Mlp", "step_many", "selftest_philox", "selftest_sqrt",
-                "selftest_copy"):
+                "selftest_copy", "mlp_forward_static"):
         from . import discharge
 
         return getattr(discharge, name)

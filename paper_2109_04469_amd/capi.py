@@ -127,6 +127,7 @@ def load():
     L.pic_mlp_train_step.argtypes = [P, P, P, ctypes.c_int, f32, f32, f32, f32, f32]
     L.pic_mlp_free.argtypes = [P]
     L.pic_mlp_free.restype = None
+    L.pic_mlp_forward_static.argtypes = [ctypes.c_int] * 4 + [P, P, ctypes.c_int, P, P]
     L.pic_sync.argtypes = [P]
     L.pic_set_field.argtypes = [P, P]
     L.pic_get_field.argtypes = [P, P, P, P, P, P]
@@ -153,6 +154,7 @@ def load():
                  "pic_load_profile", "pic_wall_moments", "pic_get_monitors", "pic_set_launch", "pic_tune", "pic_mlp_workspace_bytes", "pic_mlp_init", "pic_mlp_num_params",
                  "pic_mlp_set_params", "pic_mlp_get_params", "pic_mlp_forward", "pic_mlp_grad",
                  "pic_mlp_get_grad", "pic_mlp_get_loss", "pic_mlp_adam", "pic_mlp_train_step",
+                 "pic_mlp_forward_static",
                  "pic_sync", "pic_set_field", "pic_get_field", "pic_measure", "pic_moments",
                  "pic_get_counters", "pic_get_decisions", "pic_get_derived",
                  "pic_selftest_philox", "pic_selftest_sqrt", "pic_selftest_copy", "pic_timing",

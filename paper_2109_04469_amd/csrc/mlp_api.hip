@@ -3,6 +3,7 @@
 // FP32 activations and accumulation, mean-squared-error loss and AdamW.
 // Host code only; the arithmetic runs in k_mlp.hip.
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -254,3 +255,83 @@ void pic_mlp_free(pic_mlp* m) {
 }
 
 }  // extern "C"
+
+// ---- forward pass without a workspace -------------------------------------
+// pic_mlp_forward_static keeps the BF16 weight copies and the hidden
+// activations of one call in a fixed device array instead of a caller's
+// workspace. Each GPU holds its own copy of the array (at its own address,
+// looked up once per device) for the life of the process.
+
+namespace {
+
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices];  // device address of `scratch` per device
+
+// The current device's copy of the array; its address is taken once per
+// device, with that device current.
+int scratch_here(unsigned char** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return PIC_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PIC_EHIP;
+    g_scratch[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch[dev];
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" int pic_mlp_forward_static(int n_in, int width, int depth, int n_out,
+                                      const float* params, const float* x, int batch, float* y,
+                                      void* stream) {
+  if (!params || !x || !y || batch < 1) return PIC_EINVAL;
+  const int v = check_dims(n_in, width, depth, n_out, batch);
+  if (v) return v;
+  // scratch: BF16 weights of every layer, two hidden activation buffers
+  // (alternate layers) and the pre-activations the hidden epilogue writes
+  const int nl = depth + 1;
+  int64_t nw = 0;
+  for (int l = 0; l < nl; ++l)
+    nw += (int64_t)(l == 0 ? n_in : width) * (l == nl - 1 ? n_out : width);
+  const size_t act = al((size_t)batch * (size_t)width * 4);
+  const size_t wb_bytes = al((size_t)nw * 2);
+  if (wb_bytes + 3 * act > kStaticScratchBytes) return PIC_EINVAL;
+  unsigned char* base = nullptr;
+  const int st = scratch_here(&base);
+  if (st) return st;
+  uint16_t* wb = reinterpret_cast<uint16_t*>(base);
+  float* a[2] = {reinterpret_cast<float*>(base + wb_bytes),
+                 reinterpret_cast<float*>(base + wb_bytes + act)};
+  float* z = reinterpret_cast<float*>(base + wb_bytes + 2 * act);
+  hipStream_t s = (hipStream_t)stream;
+  // the same layer loop as a network's forward pass: weights to BF16, then
+  // each layer's product with its epilogue
+  int64_t off = 0, woff = 0;
+  const float* in = x;
+  for (int l = 0; l < nl; ++l) {
+    const int di = l == 0 ? n_in : width;
+    const int dn = l == nl - 1 ? n_out : width;
+    const bool last = l == nl - 1;
+    HIP_TRY(launch_to_bf16(params + off, wb + woff, (int64_t)di * dn, s));
+    float* out = last ? y : a[l & 1];
+    HIP_TRY(launch_gemm_bf16(last ? EP_BIAS : EP_BIAS_GELU, in, di, 1, wb + woff, 1, di, out, dn,
+                             params + off + (int64_t)di * dn, z, batch, dn, di, s));
+    in = out;
+    off += (int64_t)di * dn + dn;
+    woff += (int64_t)di * dn;
+  }
+  return PIC_OK;
+}

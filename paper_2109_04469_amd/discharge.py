@@ -399,3 +399,21 @@ class Mlp:
             self.close()
         except Exception:
             pass
+
+
+def mlp_forward_static(dims, params, x, stream=None):
+    """y = network(x) through pic_mlp_forward_static, which needs no
+    workspace: dims = (n_in, width, depth, n_out); params, x: float32 device
+    tensors (the parameter vector of Mlp.set_params, [batch, n_in]); returns
+    [batch, n_out] after the stream has run the call."""
+    L = capi.load()
+    n_in, width, depth, n_out = (int(v) for v in dims)
+    params = params.contiguous()
+    x = x.contiguous()
+    y = torch.empty((x.shape[0], n_out), dtype=torch.float32, device=x.device)
+    s = stream if stream is not None else torch.cuda.current_stream(x.device)
+    check(L.pic_mlp_forward_static(n_in, width, depth, n_out, _ptr(params), _ptr(x), int(x.shape[0]),
+                                   _ptr(y), ctypes.c_void_p(s.cuda_stream)), "pic_mlp_forward_static")
+    s.synchronize()
+    return y
+
