@@ -348,6 +348,16 @@ void pic_batch_free(pic_batch* b);
  * the tiles and every per-slot decision are the same for any grid. */
 int pic_set_launch(pic_handle* h, int decide_wg_per_cu, int emit_wg_per_cu);
 
+/* Pipelined electron steps on (1) or off (0, the default). On, within one
+ * pic_step call the electron emit of a step also takes the next step's
+ * electron decisions (push, candidacy, walls, collision process, deposit),
+ * so that step has no decide pass of its own; this applies to steps that
+ * are not the last of the call, not ion steps, not followed by a cell sort
+ * or pool repack and not measuring. The arithmetic is the same: results are
+ * identical bit for bit either way (Sec. 2 defines one step; the pipeline
+ * only regroups its work across kernels). */
+int pic_set_pipeline(pic_handle* h, int on);
+
 /* Picks the launch shape by measurement: advances the discharge by
  * steps_per_trial steps per candidate (every decide shape, then every emit
  * shape), timing the electron decide and emit kernels with events, and keeps

@@ -171,10 +171,14 @@ __device__ __forceinline__ void record_arrival(const PartArgs& a, int64_t slot, 
   if (bin >= 0 && bin < a.nbins) atomicAdd(&a.fedf[(int64_t)wall * a.nbins + bin], 1ull);
 }
 
+// pool index unknown to the caller: decide_rare reads it from a.idin
+constexpr uint32_t kNoId = 0xFFFFFFFFu;
+
 template <int SP, bool MEASURE>
 __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long long* s_cnt,
                                             int64_t slot, bool cand, double& x, double& vx,
-                                            uint32_t& c, uint32_t& o, uint32_t& b) {
+                                            uint32_t& c, uint32_t& o, uint32_t& b,
+                                            uint32_t pid = kNoId) {
   const double L = a.L;
   const uint32_t step = a.step;
   bool alive = true;
@@ -226,7 +230,7 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
       // electron candidate: the process at this speed decides whether a
       // second electron and an ion are born
       atomicAdd(&s_cnt[C_E_CAND], 1ull);
-      const uint32_t id = a.idin[slot];
+      const uint32_t id = pid != kNoId ? pid : a.idin[slot];
       const double vy = a.pvy[id], vz = a.pvz[id];
       const double g2 = sqrt(vx * vx + vy * vy + vz * vz);
       const double tv = g2 * a.inv_dv;
@@ -264,7 +268,7 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
 // collect in LDS until one flush at the end. sH (and, measuring, sEW) are all
 // zero on entry and on exit; sE holds a's field; s_lo > s_hi on entry and on
 // exit, and the caller synchronises the workgroup before the next call.
-template <int SP, bool MEASURE>
+template <int SP, bool MEASURE, bool STORE = false>
 __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int t_end, int t_step,
                                              int64_t n_push, int64_t n_tot, const double* sE,
                                              unsigned long long* sH, double* sEW,
@@ -351,6 +355,26 @@ __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int
       for (int q = 0; q < 4; ++q)
         if (need[q])
           decide_rare<SP, MEASURE>(a, s_cnt, s0 + q, cand[q], xs[q], vxs[q], c[q], o[q], b[q]);
+      if (STORE) {
+        // the pushed state (mirrored where reflected) replaces the slot's
+        // input, so the emit and the queued-slot work of this pass need not
+        // push again; every slot of the run was read above by this thread
+        double* xw = const_cast<double*>(a.xin);
+        double* vw = const_cast<double*>(a.vxin);
+        if (full && s0 + 3 < n_push) {
+          reinterpret_cast<double2*>(xw + s0)[0] = make_double2(xs[0], xs[1]);
+          reinterpret_cast<double2*>(xw + s0)[1] = make_double2(xs[2], xs[3]);
+          reinterpret_cast<double2*>(vw + s0)[0] = make_double2(vxs[0], vxs[1]);
+          reinterpret_cast<double2*>(vw + s0)[1] = make_double2(vxs[2], vxs[3]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (s0 + q < n_push) {
+              xw[s0 + q] = xs[q];
+              vw[s0 + q] = vxs[q];
+            }
+        }
+      }
 
       // deposit of the new positions (an ionization electron is born at its
       // parent's position), combined when the four share a cell
@@ -451,7 +475,7 @@ __device__ __forceinline__ void clear_next_totals(const PartArgs& a) {
     a.tcnt_next[i] = 0ull;
 }
 
-template <int SP, bool MEASURE>
+template <int SP, bool MEASURE, bool STORE>
 __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nx = a.nx;
@@ -499,8 +523,8 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
   }
   __syncthreads();
 
-  decide_tiles<SP, MEASURE>(a, blockIdx.x, ntiles, gridDim.x, n_push, n_tot, sE, sH, sEW, sEEPF,
-                            s_lo, s_hi, s_cnt);
+  decide_tiles<SP, MEASURE, STORE>(a, blockIdx.x, ntiles, gridDim.x, n_push, n_tot, sE, sH, sEW,
+                                   sEEPF, s_lo, s_hi, s_cnt);
 
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
   if (MEASURE) {
@@ -546,6 +570,42 @@ __device__ __forceinline__ void reload(const PartArgs& a, const double* E, int64
   repush(a, E, c, x, vx);
 }
 
+// Electron decision of step b.step for the single slot `slot` of that
+// step's arrays, holding x, vx (the state the previous step left) and pool
+// entry id: field at the particle from E (b's field, in LDS or global
+// memory), the push, the candidacy draw (word slot mod 4 of the block
+// (step, slot / 4, 4, 0)), and for the few slots that left the gap or are
+// candidates the wall and collision decisions. The same arithmetic as
+// decide_tiles, one slot at a time. x and vx become the pushed state
+// (mirrored when reflected); c, o, bb: decision code, own outputs and
+// births of the slot in step b.step.
+__device__ __forceinline__ void decide_one(const PartArgs& b, const double* E, int64_t slot,
+                                           double& x, double& vx, uint32_t id,
+                                           unsigned long long* s_cnt, uint32_t& c, uint32_t& o,
+                                           uint32_t& bb) {
+  int j;
+  double f;
+  int64_t w1;
+  cell_of(x, b.inv_dx, b.nx, j, f, w1);
+  push(E, j, f, b.acc, b.dts, x, vx);
+  const uint4 r = draw(b.step, (uint32_t)(slot >> 2), 0, 4, b.seed, b.run);
+  const int q = (int)(slot & 3);
+  const uint32_t w = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
+  const bool cand = (uint64_t)w < (b.no_coll ? 0ull : b.pcoll_thr);
+  c = kCodePushed;
+  o = 1u;
+  bb = 0u;
+  if (cand || !(x >= 0.0 && x <= b.L) || !isfinite(vx))
+    decide_rare<0, false>(b, s_cnt, slot, cand, x, vx, c, o, bb, id);
+}
+
+// Tile totals word of one slot's outcome: outputs | births << 16 |
+// queued << 32.
+__device__ __forceinline__ unsigned long long totals_word(uint32_t c, uint32_t o, uint32_t bb) {
+  return (unsigned long long)o | ((unsigned long long)bb << 16) |
+         ((unsigned long long)(outcome<0>(c).rare ? 1u : 0u) << 32);
+}
+
 // tile totals each thread reads at once per step of a strided run
 constexpr int kStrideLoads = 8;
 
@@ -579,13 +639,27 @@ __device__ __forceinline__ void emit_empty(DevCtl* ctl, int par) {
 // used by alternate tiles, and every wave scans a tile's totals itself, so
 // a tile needs one workgroup barrier; queued slots take their places in
 // slot order from the same scans.
-template <int SP, int STAGE_PER>
+//
+// MODE 0: the input holds the state before the push, which is repeated
+// here (sE: a's field). MODE 1: the input holds the pushed state (k_decide
+// stored it), written out as it is. MODE 2 (electrons): as MODE 1, and each
+// output that needs no queued work is then decided for the next step b
+// (decide_one with b's field in sE): the output slot receives the pushed
+// state of that step, its decision code goes to b.codes, its deposit to the
+// LDS histogram sH (flushed by the caller over [jlo, jhi]), its outcome to
+// the next pass's tile totals b.tcnt, its events to s_cnt.
+template <int SP, int STAGE_PER, int MODE = 0>
 __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, int t_step,
                                            int ntiles, int64_t n_tot, int64_t bbase, double* sE,
                                            uint32_t (*s_wtot)[kEPairs][kBlock / kWave],
                                            uint32_t (*s_wr)[kEPairs][kBlock / kWave],
                                            uint32_t (*s_ps)[3][kBlock / kWave],
-                                           uint64_t (*s_red)[kBlock / kWave]) {
+                                           uint64_t (*s_red)[kBlock / kWave],
+                                           const PartArgs* b = nullptr,
+                                           unsigned long long* sH = nullptr,
+                                           unsigned long long* s_cnt = nullptr,
+                                           int* jlo_out = nullptr, int* jhi_out = nullptr) {
+  static_assert(MODE != 2 || SP == 0, "only electron passes decide the next step");
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
@@ -604,7 +678,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       v[u] = t < t0 ? a.tcnt[t] : 0ull;
     }
     if (!staged) {
-      stage_field<kBlock, STAGE_PER>(sE, a.E, a.nx);
+      if (MODE != 1) stage_field<kBlock, STAGE_PER>(sE, MODE == 2 ? b->E : a.E, a.nx);
       staged = true;
     }
 #pragma unroll
@@ -614,7 +688,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       pr += v[u] >> 32;
     }
   }
-  if (!staged) stage_field<kBlock, STAGE_PER>(sE, a.E, a.nx);
+  if (!staged && MODE != 1) stage_field<kBlock, STAGE_PER>(sE, MODE == 2 ? b->E : a.E, a.nx);
   po = wave_sum<unsigned long long>(po);
   pb = wave_sum<unsigned long long>(pb);
   pr = wave_sum<unsigned long long>(pr);
@@ -631,6 +705,9 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
     prefR += (int64_t)s_red[2][w];
   }
 
+  // MODE 2: this lane's deposit run (cell jr, weights of nodes jr, jr + 1)
+  int jr = -1, jlo = INT_MAX, jhi = -1;
+  unsigned long long h0 = 0ull, h1 = 0ull;
   for (int t = t0; t < t1; t += t_step) {
     const int p = ((t - t0) / t_step) & 1;
     const int64_t base = (int64_t)t * kTile;
@@ -726,6 +803,11 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
     const uint32_t tile_ob = (uint32_t)__builtin_amdgcn_readlane((int)si, nseg - 1);
     const uint32_t tile_r = (uint32_t)__builtin_amdgcn_readlane((int)sri, nseg - 1);
     const int wv = __builtin_amdgcn_readfirstlane(wave);
+    // MODE 2: outcomes of the next step per output tile, relative to the
+    // tile of this tile's first output (its outputs span at most 2 kTile
+    // slots, so three tiles)
+    const int64_t tA = prefO / kTile;
+    uint32_t nt[3] = {0u, 0u, 0u};
 
 #pragma unroll
     for (int k = 0; k < kEPairs; ++k) {
@@ -749,10 +831,53 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         if (in && !rare && oc.own) {
           const int64_t dest = prefO + (int64_t)(off & 0xFFFFu);
           double x = px[q], vx = pvx[q];
-          repush(a, sE, c, x, vx);
+          if (MODE == 0) repush(a, sE, c, x, vx);
+          if (MODE == 2 && dest < a.cap) {
+            uint32_t c2, o2, b2;
+            decide_one(*b, sE, dest, x, vx, pid[q], s_cnt, c2, o2, b2);
+            b->codes[dest] = (uint8_t)c2;
+            const uint32_t rel = (uint32_t)(dest / kTile - tA);
+            const uint32_t word = o2 | (b2 << 11) | ((outcome<0>(c2).rare ? 1u : 0u) << 22);
+            nt[0] += rel == 0u ? word : 0u;
+            nt[1] += rel == 1u ? word : 0u;
+            nt[2] += rel == 2u ? word : 0u;
+            if (o2) {
+              int jd;
+              double fd;
+              int64_t w1;
+              cell_of(x, b->inv_dx, b->nx, jd, fd, w1);
+              if (jd != jr) {
+                if (jr >= 0) {
+                  atomicAdd(&sH[jr], h0);
+                  atomicAdd(&sH[jr + 1], h1);
+                }
+                jr = jd;
+                h0 = h1 = 0ull;
+                jlo = min(jlo, jd);
+                jhi = max(jhi, jd + 1);
+              }
+              h0 += (unsigned long long)o2 * (unsigned long long)(kOne32 - w1);
+              h1 += (unsigned long long)o2 * (unsigned long long)w1;
+            }
+          }
           if (dest < a.cap) store3(a, dest, x, vx, pid[q]);
         }
         if (in) off += oc.own | (oc.birth << 16);
+      }
+    }
+    if (MODE == 2) {
+      // this wave's share of the next pass's tile totals (per wave at most
+      // 2 * kPPT * 64 outputs, kPPT * 64 births and queued slots: 11, 11
+      // and 10 bits), widened to the totals' layout
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const uint32_t ws = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan_dpp(nt[r]), kWave - 1);
+        if (lane == 0 && ws) {
+          const unsigned long long tot = (unsigned long long)(ws & 0x7FFu) |
+                                         ((unsigned long long)((ws >> 11) & 0x7FFu) << 16) |
+                                         ((unsigned long long)(ws >> 22) << 32);
+          atomicAdd(&b->tcnt[tA + r], tot);
+        }
       }
     }
     if (t_step > 1 && t + t_step < t1) {
@@ -793,12 +918,26 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       if (SP == 0) ctl->pool_n[SP] += prefB;
       ctl->pool_n[other] += prefB;
       if (ctl->pool_n[SP] > a.pcap || ctl->pool_n[other] > a.bpcap) latch_error(ctl, kErrCapacity);
+      if (MODE == 2) {
+        // the next step pushes every output of this one
+        const int64_t np = prefO < a.cap ? prefO : a.cap;
+        if (b->record) ctl->ncodes[SP] = np;
+        atomicAdd(&ctl->counters[C_E_PUSHED], (unsigned long long)np);
+      }
     }
+  }
+  if (MODE == 2) {
+    if (jr >= 0) {
+      atomicAdd(&sH[jr], h0);
+      atomicAdd(&sH[jr + 1], h1);
+    }
+    *jlo_out = jlo;
+    *jhi_out = jhi;
   }
   __syncthreads();  // the field and the totals may be reused by the caller
 }
 
-template <int SP>
+template <int SP, int MODE>
 __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   double* sE = reinterpret_cast<double*>(smem);
@@ -837,8 +976,72 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   }
   if (t0 >= t1) return;
 
-  emit_tiles<SP, (kMaxNx + kBlock - 1) / kBlock>(a, t0, t1, t_step, ntiles, n_tot, bbase, sE,
-                                                  s_wtot, s_wr, s_ps, s_red);
+  emit_tiles<SP, (kMaxNx + kBlock - 1) / kBlock, MODE>(a, t0, t1, t_step, ntiles, n_tot, bbase,
+                                                        sE, s_wtot, s_wr, s_ps, s_red);
+}
+
+// The electron emit of pass a fused with the electron decisions of the next
+// step b (emit_tiles MODE 2): a's input holds pushed, decided state; the
+// outputs that need no queued work leave pushed and decided for b, so the
+// next step has no decide pass of its own. Contiguous runs of tiles per
+// workgroup (as k_emit for electrons); b's field in LDS with the deposit
+// histogram, flushed once per workgroup.
+__global__ __launch_bounds__(kBlock) void k_emit_decide(PartArgs a, PartArgs b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nx = a.nx;
+  double* sE = reinterpret_cast<double*>(smem);
+  unsigned long long* sH = reinterpret_cast<unsigned long long*>(sE + nx);
+  __shared__ uint32_t s_wtot[2][kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_wr[2][kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_ps[2][3][kBlock / kWave];
+  __shared__ uint64_t s_red[3][kBlock / kWave];
+  __shared__ unsigned long long s_cnt[NCOUNTERS];
+  __shared__ int s_lo, s_hi;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  DevCtl* ctl = a.ctl;
+  const int par = a.parity;
+  for (int j = tid; j < nx; j += kBlock) sH[j] = 0ull;
+  if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
+  if (tid == 0) {
+    s_lo = INT_MAX;
+    s_hi = -1;
+  }
+
+  int64_t n_tot = uniform64(ctl->n_e[par]);
+  if (n_tot > a.cap) n_tot = a.cap;  // the decide has latched the error
+  const int64_t bbase = uniform64(ctl->n_i[par]);
+  const int ntiles = uniform32((int)((n_tot + kTile - 1) / kTile));
+  if (ntiles == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
+      emit_empty<0>(ctl, par);
+      if (b.record) ctl->ncodes[0] = 0;
+    }
+    return;
+  }
+  const int t0 = uniform32((int)((int64_t)ntiles * blockIdx.x / gridDim.x));
+  const int t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
+  __syncthreads();  // sH, s_cnt, s_lo, s_hi set
+  if (t0 >= t1) return;
+
+  int jlo = INT_MAX, jhi = -1;
+  emit_tiles<0, (kMaxNx + kBlock - 1) / kBlock, 2>(a, t0, t1, 1, ntiles, n_tot, bbase, sE, s_wtot,
+                                                   s_wr, s_ps, s_red, &b, sH, s_cnt, &jlo, &jhi);
+  // one flush of the deposit range of this workgroup's outputs
+  jlo = wave_min(jlo);
+  jhi = wave_max(jhi);
+  if (lane == 0) {
+    atomicMin(&s_lo, jlo);
+    atomicMax(&s_hi, jhi);
+  }
+  __syncthreads();
+  const int lo = s_lo, hi = s_hi;
+  for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += kBlock) {
+    const unsigned long long v = sH[j];
+    if (v) atomicAdd(&b.dep_own[j], v);
+  }
+  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
 }
 
 // ---------------------------------------------------------------------------
@@ -882,18 +1085,58 @@ __device__ __forceinline__ void aniso_dir(double ex, double ey, double ez, doubl
   nz = c * ez + sn * (cp * b1z + sp * b2z);
 }
 
+// deposit_global with weight mul (an ionization electron and its parent
+// share a position)
+__device__ __forceinline__ void deposit_global_n(unsigned long long* dep, double x, double inv_dx,
+                                                 int nx, uint32_t mul) {
+  int j;
+  double f;
+  int64_t w1;
+  cell_of(x, inv_dx, nx, j, f, w1);
+  atomicAdd(&dep[j], (unsigned long long)mul * (unsigned long long)(kOne32 - w1));
+  atomicAdd(&dep[j + 1], (unsigned long long)mul * (unsigned long long)w1);
+}
+
+// An electron output of pass a at slot dest (state x, vx after a's step,
+// pool entry id already written) decided for the next step b, one slot at a
+// time: decide_one with b's field from global memory, the decision code,
+// the next pass's tile totals and the deposit with global atomics, and the
+// pushed state stored at the slot.
+__device__ __forceinline__ void next_step_output(const PartArgs& a, const PartArgs& b,
+                                                 unsigned long long* s_cnt, int64_t dest,
+                                                 double x, double vx, uint32_t id) {
+  uint32_t c2, o2, b2;
+  decide_one(b, b.E, dest, x, vx, id, s_cnt, c2, o2, b2);
+  b.codes[dest] = (uint8_t)c2;
+  atomicAdd(&b.tcnt[dest / kTile], totals_word(c2, o2, b2));
+  if (o2) deposit_global_n(b.dep_own, x, b.inv_dx, b.nx, o2);
+  store3(a, dest, x, vx, id);
+}
+
 // VAR: the method-variant paths (anisotropic elastic scattering, Opal
 // sharing) are compiled in; without them the kernels stay smaller.
-template <int SP, bool VAR>
+// PUSHED: the slot's input holds the pushed state (k_decide stored it), so
+// it is not pushed again. FUSED (electrons, with PUSHED): the outputs are
+// then decided for the next step nb (next_step_output).
+template <int SP, bool VAR, bool PUSHED = false, bool FUSED = false>
 __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long* s_cnt,
                                           int64_t slot, uint32_t c, int64_t dest, int64_t r,
-                                          int64_t bbase) {
+                                          int64_t bbase, const PartArgs* nb = nullptr) {
+  static_assert(!FUSED || (PUSHED && SP == 0), "only pushed electron slots are fused");
   const uint32_t step = a.step;
   const double L = a.L;
   const int64_t bdest = bbase + r;
   double x, vx, vy, vz;
   uint32_t id;
-  reload(a, a.E, slot, c, x, vx, id, vy, vz);
+  if (PUSHED) {
+    x = a.xin[slot];
+    vx = a.vxin[slot];
+    id = a.idin[slot];
+    vy = a.pvy[id];
+    vz = a.pvz[id];
+  } else {
+    reload(a, a.E, slot, c, x, vx, id, vy, vz);
+  }
   const Outcome oc = outcome<SP>(c);
   bool child = false;
   double cvx = 0, cvy = 0, cvz = 0, bxp = 0, bvx = 0, bvy = 0, bvz = 0;
@@ -1004,15 +1247,30 @@ __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long*
   }
   if (oc.own) {
     // the particle keeps its pool entry
-    if (dest < a.cap) store3(a, dest, x, vx, id);
-    a.pvy[id] = vy;
-    a.pvz[id] = vz;
-    if (child) {
-      const int64_t cid = a.ctl->pbase[SP] + r;
-      if (dest + 1 < a.cap && cid < a.pcap) {
-        store3(a, dest + 1, x, cvx, (uint32_t)cid);
-        a.pvy[cid] = cvy;
-        a.pvz[cid] = cvz;
+    if (FUSED) {
+      // pool entries first: the next step's decision reads them
+      a.pvy[id] = vy;
+      a.pvz[id] = vz;
+      if (dest < a.cap) next_step_output(a, *nb, s_cnt, dest, x, vx, id);
+      if (child) {
+        const int64_t cid = a.ctl->pbase[SP] + r;
+        if (dest + 1 < a.cap && cid < a.pcap) {
+          a.pvy[cid] = cvy;
+          a.pvz[cid] = cvz;
+          next_step_output(a, *nb, s_cnt, dest + 1, x, cvx, (uint32_t)cid);
+        }
+      }
+    } else {
+      if (dest < a.cap) store3(a, dest, x, vx, id);
+      a.pvy[id] = vy;
+      a.pvz[id] = vz;
+      if (child) {
+        const int64_t cid = a.ctl->pbase[SP] + r;
+        if (dest + 1 < a.cap && cid < a.pcap) {
+          store3(a, dest + 1, x, cvx, (uint32_t)cid);
+          a.pvy[cid] = cvy;
+          a.pvz[cid] = cvz;
+        }
       }
     }
   }
@@ -1028,7 +1286,7 @@ __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long*
   }
 }
 
-template <int SP, bool VAR>
+template <int SP, bool VAR, bool PUSHED>
 __global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
   __shared__ unsigned long long s_cnt[NCOUNTERS];
   const int tid = threadIdx.x;
@@ -1041,7 +1299,31 @@ __global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
   const int64_t nb = gridDim.x;
   for (int64_t i = (int64_t)blockIdx.x + nb * tid; i < n; i += nb * kBlock) {
     const uint4 q = a.rq[i];
-    rare_slot<SP, VAR>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
+    rare_slot<SP, VAR, PUSHED>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
+  }
+  __syncthreads();
+  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
+}
+
+// The queued slots of electron pass a (pushed input), each output then
+// decided for the next step b; and a's tile totals, read by a's emit, are
+// zeroed for the pass after b, which adds into the same buffer.
+template <bool VAR>
+__global__ __launch_bounds__(kBlock) void k_tail2(PartArgs a, PartArgs b) {
+  __shared__ unsigned long long s_cnt[NCOUNTERS];
+  const int tid = threadIdx.x;
+  if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < a.max_tiles;
+       i += (int64_t)gridDim.x * kBlock)
+    a.tcnt[i] = 0ull;
+  __syncthreads();
+  const int64_t n = a.ctl->n_rare[0];
+  const int64_t bbase = a.ctl->n_i[a.parity];
+  const int64_t nblk = gridDim.x;
+  for (int64_t i = (int64_t)blockIdx.x + nblk * tid; i < n; i += nblk * kBlock) {
+    const uint4 q = a.rq[i];
+    rare_slot<0, VAR, true, true>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase,
+                                  &b);
   }
   __syncthreads();
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
@@ -1054,7 +1336,7 @@ __global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
 // The two are independent: the field goes to the other E buffer, and the
 // queued slots read the E of this step.
 
-template <int SP, bool VAR>
+template <int SP, bool VAR, bool PUSHED>
 __global__ __launch_bounds__(kFieldThreads) void k_tail(FieldArgs f, PartArgs a) {
   if (blockIdx.x == 0) {
     field_block(f);
@@ -1071,21 +1353,26 @@ __global__ __launch_bounds__(kFieldThreads) void k_tail(FieldArgs f, PartArgs a)
   const int64_t nb = gridDim.x - 1;
   for (int64_t i = (int64_t)(blockIdx.x - 1) + nb * tid; i < n; i += nb * kFieldThreads) {
     const uint4 q = a.rq[i];
-    rare_slot<SP, VAR>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
+    rare_slot<SP, VAR, PUSHED>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
   }
   __syncthreads();
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
 }
 
 hipError_t launch_tail(int species, const FieldArgs& f, const PartArgs& a, int rare_blocks,
-                       hipStream_t s) {
+                       hipStream_t s, bool pushed) {
   if (f.nx > kMaxNx || f.nx < 3 || rare_blocks < 1) return hipErrorInvalidValue;
-  if (species == 0 && a.model)
-    hipLaunchKernelGGL((k_tail<0, true>), dim3(1 + rare_blocks), dim3(kFieldThreads), 0, s, f, a);
-  else if (species == 0)
-    hipLaunchKernelGGL((k_tail<0, false>), dim3(1 + rare_blocks), dim3(kFieldThreads), 0, s, f, a);
+  const dim3 g(1 + rare_blocks), t(kFieldThreads);
+  if (species == 1)
+    hipLaunchKernelGGL((k_tail<1, false, false>), g, t, 0, s, f, a);
+  else if (pushed && a.model)
+    hipLaunchKernelGGL((k_tail<0, true, true>), g, t, 0, s, f, a);
+  else if (pushed)
+    hipLaunchKernelGGL((k_tail<0, false, true>), g, t, 0, s, f, a);
+  else if (a.model)
+    hipLaunchKernelGGL((k_tail<0, true, false>), g, t, 0, s, f, a);
   else
-    hipLaunchKernelGGL((k_tail<1, false>), dim3(1 + rare_blocks), dim3(kFieldThreads), 0, s, f, a);
+    hipLaunchKernelGGL((k_tail<0, false, false>), g, t, 0, s, f, a);
   return hipGetLastError();
 }
 
@@ -1320,24 +1607,29 @@ static int clamp_grid(int64_t g, int64_t max_tiles) {
   return (int)g;
 }
 
+static size_t emit_decide_lds(int nx) { return (size_t)nx * 16; }
+
 PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, int64_t max_tiles) {
   PartLaunch c{};
   for (int m = 0; m < 2; ++m) {
     c.lds_decide[m] = decide_lds(nx, m == 1, nbins);
     int bpc;
     if (species == 0)
-      bpc = m ? blocks_per_cu(k_decide<0, true>, c.lds_decide[m], kDB)
-              : blocks_per_cu(k_decide<0, false>, c.lds_decide[m], kDB);
+      bpc = m ? blocks_per_cu(k_decide<0, true, false>, c.lds_decide[m], kDB)
+              : blocks_per_cu(k_decide<0, false, false>, c.lds_decide[m], kDB);
     else
-      bpc = blocks_per_cu(k_decide<1, false>, c.lds_decide[m], kDB);
+      bpc = blocks_per_cu(k_decide<1, false, false>, c.lds_decide[m], kDB);
     c.grid_decide[m] = clamp_grid((int64_t)bpc * num_cu, max_tiles);
     c.bpc_decide[m] = bpc;
   }
   c.lds_emit = emit_lds(nx);
-  const int bpc = species == 0 ? blocks_per_cu(k_emit<0>, c.lds_emit)
-                               : blocks_per_cu(k_emit<1>, c.lds_emit);
+  const int bpc = species == 0 ? blocks_per_cu(k_emit<0, 0>, c.lds_emit)
+                               : blocks_per_cu(k_emit<1, 0>, c.lds_emit);
   c.grid_emit = clamp_grid((int64_t)bpc * num_cu, max_tiles);
   c.bpc_emit = bpc;
+  c.lds_emit_decide = emit_decide_lds(nx);
+  c.bpc_emit_decide = species == 0 ? blocks_per_cu(k_emit_decide, c.lds_emit_decide) : 1;
+  c.grid_emit_decide = clamp_grid((int64_t)c.bpc_emit_decide * num_cu, max_tiles);
   c.grid_rare = num_cu * 2;
   c.max_tiles = max_tiles;
   return c;
@@ -1350,34 +1642,66 @@ void particle_launch_set(PartLaunch& c, int num_cu, int kd, int ke) {
   }
   const int k = ke < 1 ? 1 : (ke > c.bpc_emit ? c.bpc_emit : ke);
   c.grid_emit = clamp_grid((int64_t)k * num_cu, c.max_tiles);
+  const int k2 = ke < 1 ? 1 : (ke > c.bpc_emit_decide ? c.bpc_emit_decide : ke);
+  c.grid_emit_decide = clamp_grid((int64_t)k2 * num_cu, c.max_tiles);
 }
 
 hipError_t launch_particle_kernel(int kernel, int species, bool measure, const PartArgs& a,
-                                  const PartLaunch& c, hipStream_t s) {
+                                  const PartLaunch& c, hipStream_t s, int flags) {
   const int m = (species == 0 && measure) ? 1 : 0;
+  const bool store = (flags & kLaunchStore) != 0;
+  const bool pushed = (flags & kLaunchPushed) != 0;
+  if (species == 1 && (store || pushed)) return hipErrorInvalidValue;
   if (kernel == 0) {
+    const dim3 g(c.grid_decide[m]), t(kDB);
+    const size_t lds = c.lds_decide[m];
     if (species == 1)
-      hipLaunchKernelGGL((k_decide<1, false>), dim3(c.grid_decide[0]), dim3(kDB),
-                         c.lds_decide[0], s, a);
+      hipLaunchKernelGGL((k_decide<1, false, false>), g, t, lds, s, a);
+    else if (m && store)
+      hipLaunchKernelGGL((k_decide<0, true, true>), g, t, lds, s, a);
     else if (m)
-      hipLaunchKernelGGL((k_decide<0, true>), dim3(c.grid_decide[1]), dim3(kDB),
-                         c.lds_decide[1], s, a);
+      hipLaunchKernelGGL((k_decide<0, true, false>), g, t, lds, s, a);
+    else if (store)
+      hipLaunchKernelGGL((k_decide<0, false, true>), g, t, lds, s, a);
     else
-      hipLaunchKernelGGL((k_decide<0, false>), dim3(c.grid_decide[0]), dim3(kDB),
-                         c.lds_decide[0], s, a);
+      hipLaunchKernelGGL((k_decide<0, false, false>), g, t, lds, s, a);
   } else if (kernel == 1) {
-    if (species == 0)
-      hipLaunchKernelGGL((k_emit<0>), dim3(c.grid_emit), dim3(kBlock), c.lds_emit, s, a);
+    const dim3 g(c.grid_emit), t(kBlock);
+    if (species == 1)
+      hipLaunchKernelGGL((k_emit<1, 0>), g, t, c.lds_emit, s, a);
+    else if (pushed)
+      hipLaunchKernelGGL((k_emit<0, 1>), g, t, c.lds_emit, s, a);
     else
-      hipLaunchKernelGGL((k_emit<1>), dim3(c.grid_emit), dim3(kBlock), c.lds_emit, s, a);
+      hipLaunchKernelGGL((k_emit<0, 0>), g, t, c.lds_emit, s, a);
   } else {
-    if (species == 0 && a.model)
-      hipLaunchKernelGGL((k_rare<0, true>), dim3(c.grid_rare), dim3(kBlock), 0, s, a);
-    else if (species == 0)
-      hipLaunchKernelGGL((k_rare<0, false>), dim3(c.grid_rare), dim3(kBlock), 0, s, a);
+    const dim3 g(c.grid_rare), t(kBlock);
+    if (species == 1)
+      hipLaunchKernelGGL((k_rare<1, false, false>), g, t, 0, s, a);
+    else if (pushed && a.model)
+      hipLaunchKernelGGL((k_rare<0, true, true>), g, t, 0, s, a);
+    else if (pushed)
+      hipLaunchKernelGGL((k_rare<0, false, true>), g, t, 0, s, a);
+    else if (a.model)
+      hipLaunchKernelGGL((k_rare<0, true, false>), g, t, 0, s, a);
     else
-      hipLaunchKernelGGL((k_rare<1, false>), dim3(c.grid_rare), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_rare<0, false, false>), g, t, 0, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_emit_decide(const PartArgs& a, const PartArgs& b, const PartLaunch& c,
+                              hipStream_t s) {
+  if (a.nx > kMaxNx || a.nx != b.nx) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_emit_decide, dim3(c.grid_emit_decide), dim3(kBlock), c.lds_emit_decide, s, a,
+                     b);
+  return hipGetLastError();
+}
+
+hipError_t launch_tail2(const PartArgs& a, const PartArgs& b, const PartLaunch& c, hipStream_t s) {
+  if (a.model)
+    hipLaunchKernelGGL((k_tail2<true>), dim3(c.grid_rare), dim3(kBlock), 0, s, a, b);
+  else
+    hipLaunchKernelGGL((k_tail2<false>), dim3(c.grid_rare), dim3(kBlock), 0, s, a, b);
   return hipGetLastError();
 }
 

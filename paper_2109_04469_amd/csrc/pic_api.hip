@@ -47,7 +47,7 @@ double fedf_ion_emax(double rf_voltage_v) {
 }
 
 struct Layout {
-  size_t ctl, part[2][2][2], pid[2][2], pool[2][2][2], codes[2], tcnt[2][2], rq[2], dep_e[2], dep_i[2], rho, phi, E[2], cum[2], th_cp,
+  size_t ctl, part[2][2][2], pid[2][2], pool[2][2][2], codes[2][2], tcnt[2][2], rq[2], dep_e[2], dep_i[2], rho, phi, E[2], cum[2], th_cp,
       th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, fedf[2], sort_cnt, sort_seg, total;
   int64_t max_tiles[2];
   int sort_blocks;
@@ -99,7 +99,7 @@ Layout make_layout(const pic_params* p, const pic_xsec* xs) {
       L.pid[s][b] = take((size_t)cap * sizeof(uint32_t));
       for (int q = 0; q < 2; ++q) L.pool[s][b][q] = take((size_t)pool_capacity(cap) * 8);
     }
-    L.codes[s] = take((size_t)cap);
+    for (int b = 0; b < 2; ++b) L.codes[s][b] = take((size_t)cap);
     for (int b = 0; b < 2; ++b) L.tcnt[s][b] = take((size_t)L.max_tiles[s] * sizeof(uint64_t));
     L.rq[s] = take((size_t)cap * 16);
   }
@@ -242,7 +242,9 @@ PartArgs particle_args(pic_handle* h, int sp, int parity) {
   a.tcnt = h->tcnt[sp][h->tsel[sp]];
   a.tcnt_next = h->tcnt[sp][h->tsel[sp] ^ 1];
   a.rq = h->rq[sp];
-  a.codes = h->codes[sp];
+  // decision codes of alternate passes in alternate buffers: a pass fused
+  // with the next step's decisions reads one and writes the other
+  a.codes = h->codes[sp][h->csel[sp]];
   a.acc_ew = h->acc_ew;
   a.eepf = h->eepf;
   a.fedf = h->fedf[sp];
@@ -370,16 +372,30 @@ constexpr int kTailRareBlocks = 128;
 //   then either the tail (queued slots of the last pass + field(n+1)) when
 //   another step follows, or the last pass's rare kernel alone;
 //   then a sort or repack of each species when due.
+//
+// Electron steps are pipelined where the schedule allows: the emit of step n
+// then also decides step n+1 (k_emit_decide, k_tail2), so step n+1 has no
+// decide pass. That needs the field of step n+1 before the emit of step n,
+// so it applies to steps that are not the last of a call, not ion steps
+// (the ions' deposit enters that field), not followed by a sort or repack
+// (slots move) and not measuring:
+//   [field(n)] [e_decide(n), storing the pushed state] field(n+1)
+//   e_emit_decide(n) e_tail2(n)
+// A step whose electrons were decided that way (e_pushed) runs e_emit and
+// the electron queued slots on the pushed state.
 struct StepPlan {
   bool field_first;  // solve this step's field before the passes
   FieldArgs ff;
   bool measure;
   PartArgs ae;
+  bool e_pushed;  // the previous step decided this step's electrons
+  bool fuse;      // this step's electron emit decides the next step
+  PartArgs ae_next;
   bool ion;
   PartArgs ai;
   int pend_sp;  // species of the last pass, whose queued slots run last
   bool tail;    // the next step's field is solved with those slots
-  FieldArgs fn;
+  FieldArgs fn; // the next step's field (with the tail, or before the fused emit)
   int post;     // 0: nothing, 1: sort, 2: repack (both species)
   SortArgs sa[2];
 };
@@ -387,7 +403,7 @@ struct StepPlan {
 // Plans the next step of h and advances the host-side schedule state past
 // it (buffer parities, step index). field_ready: this step's field was
 // solved by the previous step's tail; last: no step follows in this call.
-StepPlan plan_step(pic_handle* h, bool field_ready, bool last) {
+StepPlan plan_step(pic_handle* h, bool field_ready, bool last, bool allow_fuse) {
   StepPlan q{};
   const pic_params& p = h->p;
   const int mode = field_mode(h);
@@ -397,38 +413,44 @@ StepPlan plan_step(pic_handle* h, bool field_ready, bool last) {
   if (q.field_first) q.ff = field_args(h, mode, q.ion);
   h->e_last = par;
   q.measure = h->measuring != 0;
+  q.e_pushed = h->e_decided != 0;
+  h->e_decided = 0;
   q.ae = particle_args(h, 0, par);
   h->cur[0] ^= 1;
   h->tsel[0] ^= 1;
+  h->csel[0] ^= 1;
   q.pend_sp = 0;
   if (q.ion) {
     // the ions take this step's ionization ions with their velocities
     q.ai = particle_args(h, 1, par);
     h->cur[1] ^= 1;
     h->tsel[1] ^= 1;
+    h->csel[1] ^= 1;
     h->cur_hi ^= 1;
     q.pend_sp = 1;
   }
   h->step += 1;
-  q.tail = !last;
-  if (q.tail) q.fn = field_args(h, mode, is_ion_step(h, h->step));
   q.post = 0;
   if (p.sort_interval > 0 && h->step % p.sort_interval == 0) {
     // stable sort by cell; the pool is rebuilt in the new slot order
     q.post = 1;
-    for (int sp = 0; sp < 2; ++sp) {
-      q.sa[sp] = sort_args(h, sp, true);
-      h->cur[sp] ^= 1;
-      h->pcur[sp] ^= 1;
-    }
   } else if ((p.sort_interval == 0 || p.sort_interval > kRepackSteps) &&
              h->step % kRepackSteps == 0) {
     // pool rebuilt in slot order: drops the entries of absorbed particles
     q.post = 2;
-    for (int sp = 0; sp < 2; ++sp) {
-      q.sa[sp] = sort_args(h, sp, false);
-      h->pcur[sp] ^= 1;
-    }
+  }
+  q.fuse = allow_fuse && !last && !q.ion && q.post == 0 && !q.measure;
+  q.tail = !last && !q.fuse;
+  if (!last) q.fn = field_args(h, mode, is_ion_step(h, h->step));
+  if (q.fuse) {
+    // the next step's electron arguments, as its own plan will make them
+    q.ae_next = particle_args(h, 0, (int)(h->step & 1));
+    h->e_decided = 1;
+  }
+  for (int sp = 0; sp < 2 && q.post; ++sp) {
+    q.sa[sp] = sort_args(h, sp, q.post == 1);
+    if (q.post == 1) h->cur[sp] ^= 1;
+    h->pcur[sp] ^= 1;
   }
   return q;
 }
@@ -455,15 +477,34 @@ int launch_step(pic_handle* h, const StepPlan& q) {
     timer_end(h, PIC_TIMER_FIELD, ev);
   }
   const int e_pass = timer_begin(h);
-  for (int k = 0; k < 2; ++k) {
+  if (!q.e_pushed) {
     const int ev = h->timing >= 2 ? timer_begin(h) : -1;
-    HIP_TRY(launch_particle_kernel(k, 0, q.measure, q.ae, h->launch[0], s));
-    timer_end(h, k == 0 ? PIC_TIMER_E_DECIDE : PIC_TIMER_E_EMIT, ev);
+    HIP_TRY(launch_particle_kernel(0, 0, q.measure, q.ae, h->launch[0], s, q.fuse ? kLaunchStore : 0));
+    timer_end(h, PIC_TIMER_E_DECIDE, ev);
+  }
+  if (q.fuse) {
+    int ev = h->timing >= 2 ? timer_begin(h) : -1;
+    HIP_TRY(launch_field(q.fn, s));
+    timer_end(h, PIC_TIMER_FIELD, ev);
+    ev = h->timing >= 2 ? timer_begin(h) : -1;
+    HIP_TRY(launch_emit_decide(q.ae, q.ae_next, h->launch[0], s));
+    timer_end(h, PIC_TIMER_E_EMIT, ev);
+    ev = h->timing >= 2 ? timer_begin(h) : -1;
+    HIP_TRY(launch_tail2(q.ae, q.ae_next, h->launch[0], s));
+    timer_end(h, PIC_TIMER_E_RARE, ev);
+    timer_end(h, PIC_TIMER_ELECTRON, e_pass);
+    return launch_post(h, q, s);
+  }
+  const int pushed = q.e_pushed ? kLaunchPushed : 0;
+  {
+    const int ev = h->timing >= 2 ? timer_begin(h) : -1;
+    HIP_TRY(launch_particle_kernel(1, 0, q.measure, q.ae, h->launch[0], s, pushed));
+    timer_end(h, PIC_TIMER_E_EMIT, ev);
   }
   int pend_pass = e_pass;
   if (q.ion) {
     const int ev = h->timing >= 2 ? timer_begin(h) : -1;
-    HIP_TRY(launch_particle_kernel(2, 0, q.measure, q.ae, h->launch[0], s));
+    HIP_TRY(launch_particle_kernel(2, 0, q.measure, q.ae, h->launch[0], s, pushed));
     timer_end(h, PIC_TIMER_E_RARE, ev);
     timer_end(h, PIC_TIMER_ELECTRON, e_pass);
     const int i_pass = timer_begin(h);
@@ -475,11 +516,13 @@ int launch_step(pic_handle* h, const StepPlan& q) {
     pend_pass = i_pass;
   }
   const PartArgs& pend = q.pend_sp == 0 ? q.ae : q.ai;
+  const int pend_pushed = q.pend_sp == 0 ? pushed : 0;
   const int ev = h->timing >= 2 ? timer_begin(h) : -1;
   if (q.tail)
-    HIP_TRY(launch_tail(q.pend_sp, q.fn, pend, kTailRareBlocks, s));
+    HIP_TRY(launch_tail(q.pend_sp, q.fn, pend, kTailRareBlocks, s, pend_pushed != 0));
   else
-    HIP_TRY(launch_particle_kernel(2, q.pend_sp, q.measure, pend, h->launch[q.pend_sp], s));
+    HIP_TRY(launch_particle_kernel(2, q.pend_sp, q.measure, pend, h->launch[q.pend_sp], s,
+                                   pend_pushed));
   timer_end(h, q.pend_sp == 0 ? PIC_TIMER_E_RARE : PIC_TIMER_I_RARE, ev);
   timer_end(h, q.pend_sp == 0 ? PIC_TIMER_ELECTRON : PIC_TIMER_ION, pend_pass);
   return launch_post(h, q, s);
@@ -531,6 +574,7 @@ int check_batch_handles(pic_handle* const* hs, int n) {
 template <typename Fill>
 int replace_state(pic_handle* h, int species, int64_t n, int64_t step, Fill fill) {
   HIP_TRY(hipStreamSynchronize(h->stream));
+  h->e_decided = 0;
   const int old_par = (int)(h->step & 1), par = (int)(step & 1);
   if (old_par != par) {
     // keep the other species' count and (for electrons) deposit on the new parity
@@ -692,7 +736,8 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
       h->pid[s][b] = reinterpret_cast<uint32_t*>(w + L.pid[s][b]);
     }
     h->pcap[s] = pool_capacity(p->capacity[s]);
-    h->codes[s] = reinterpret_cast<uint8_t*>(w + L.codes[s]);
+    for (int b = 0; b < 2; ++b) h->codes[s][b] = reinterpret_cast<uint8_t*>(w + L.codes[s][b]);
+    h->csel[s] = 0;
     for (int b = 0; b < 2; ++b) h->tcnt[s][b] = reinterpret_cast<uint64_t*>(w + L.tcnt[s][b]);
     h->tsel[s] = 0;
     h->rq[s] = reinterpret_cast<uint4*>(w + L.rq[s]);
@@ -724,6 +769,8 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
   h->cur[0] = h->cur[1] = 0;
   h->pcur[0] = h->pcur[1] = 0;
   h->cur_hi = 0;
+  h->e_decided = 0;
+  h->pipeline = 0;
   h->measuring = 0;
 
   int st = PIC_OK;
@@ -840,10 +887,10 @@ int pic_step(pic_handle* h, int64_t n_steps) {
   if ((h->p.flags & PIC_FLAG_FIXED_E) && !h->field_fixed_set) return PIC_ESTATE;
   bool field_ready = false;
   for (int64_t it = 0; it < n_steps; ++it) {
-    const StepPlan q = plan_step(h, field_ready, it + 1 == n_steps);
+    const StepPlan q = plan_step(h, field_ready, it + 1 == n_steps, h->pipeline != 0);
     const int st = launch_step(h, q);
     if (st) return st;
-    field_ready = q.tail;
+    field_ready = q.tail || q.fuse;
     // keep the event backlog bounded
     if (h->ev_used.size() >= 4096) {
       const int c = timer_collect(h);
@@ -974,7 +1021,7 @@ int pic_batch_step(pic_batch* b, int64_t n_steps) {
     };
     for (int k = 0; k < m; ++k) {
       const bool last = done + k + 1 == n_steps;
-      for (int i = 0; i < n; ++i) plans[i] = plan_step(b->hs[i], field_ready, last);
+      for (int i = 0; i < n; ++i) plans[i] = plan_step(b->hs[i], field_ready, last, false);
       field_ready = !last;
       StepLaunch L{};
       L.tail = !last;
@@ -1254,7 +1301,8 @@ int pic_get_decisions(pic_handle* h, int species, uint8_t* codes, int64_t cap, i
   if (cnt > cap) return PIC_ECAPACITY;
   if (cnt > 0) {
     if (!codes) return PIC_EINVAL;
-    HIP_TRY(hipMemcpyAsync(codes, h->codes[species], (size_t)cnt, hipMemcpyDefault, h->stream));
+    HIP_TRY(hipMemcpyAsync(codes, h->codes[species][h->csel[species] ^ 1], (size_t)cnt,
+                           hipMemcpyDefault, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
   }
   return latched(h);
@@ -1263,6 +1311,12 @@ int pic_get_decisions(pic_handle* h, int species, uint8_t* codes, int64_t cap, i
 int pic_set_launch(pic_handle* h, int decide_wg_per_cu, int emit_wg_per_cu) {
   if (!h || decide_wg_per_cu < 1 || emit_wg_per_cu < 1) return PIC_EINVAL;
   for (int s = 0; s < 2; ++s) particle_launch_set(h->launch[s], h->num_cu, decide_wg_per_cu, emit_wg_per_cu);
+  return PIC_OK;
+}
+
+int pic_set_pipeline(pic_handle* h, int on) {
+  if (!h || on < 0 || on > 1) return PIC_EINVAL;
+  h->pipeline = on;
   return PIC_OK;
 }
 

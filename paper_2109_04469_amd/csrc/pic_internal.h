@@ -148,22 +148,37 @@ struct PartLaunch {
   size_t lds_decide[2];
   int grid_emit;
   size_t lds_emit;
+  int grid_emit_decide;  // the electron emit fused with the next step's decisions
+  size_t lds_emit_decide;
   int grid_rare;
   int bpc_decide[2];   // resident workgroups per CU at these LDS sizes (occupancy)
   int bpc_emit;
+  int bpc_emit_decide;
   int64_t max_tiles;
 };
 PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, int64_t max_tiles);
 // the same with k_decide at kd and k_emit at ke workgroups per CU (clamped
 // to [1, occupancy] and to the tile count)
 void particle_launch_set(PartLaunch& c, int num_cu, int kd, int ke);
-// kernel 0: k_decide, 1: k_emit, 2: k_rare (launched in this order)
+// kernel 0: k_decide, 1: k_emit, 2: k_rare (launched in this order).
+// flags (electrons only): kLaunchStore, the decide kernel stores the pushed
+// state in place of its input; kLaunchPushed, the emit and rare kernels take
+// that pushed input (no second push).
+constexpr int kLaunchStore = 1;
+constexpr int kLaunchPushed = 2;
 hipError_t launch_particle_kernel(int kernel, int species, bool measure, const PartArgs& a,
-                                  const PartLaunch& c, hipStream_t s);
+                                  const PartLaunch& c, hipStream_t s, int flags = 0);
 // field of the next step (one workgroup) together with the queued slots of
-// this step's last particle pass of `species` (rare_blocks workgroups)
+// this step's last particle pass of `species` (rare_blocks workgroups);
+// pushed: electron slots whose input holds the pushed state
 hipError_t launch_tail(int species, const FieldArgs& f, const PartArgs& a, int rare_blocks,
-                       hipStream_t s);
+                       hipStream_t s, bool pushed = false);
+// Electron pass a (pushed, decided input) fused with the decisions of the
+// next step b: the emit kernel, then the queued slots of a with their
+// outputs decided for b (and a's tile totals zeroed).
+hipError_t launch_emit_decide(const PartArgs& a, const PartArgs& b, const PartLaunch& c,
+                              hipStream_t s);
+hipError_t launch_tail2(const PartArgs& a, const PartArgs& b, const PartLaunch& c, hipStream_t s);
 // Batched launches over n discharges (n <= kMaxBatch): args and f are
 // arrays of argument blocks in device memory, one per discharge.
 constexpr int kMaxBatch = 256;
@@ -249,7 +264,8 @@ struct pic_handle {
   uint32_t* pid[2][2];    // [species][buffer] pool index per slot
   double* pool[2][2][2];  // [species][buffer][vy, vz]
   int64_t pcap[2];        // pool entries per buffer
-  uint8_t* codes[2];
+  uint8_t* codes[2][2];  // per species, two buffers used by alternate passes
+  int csel[2];           // the code buffer of the next pass of each species
   uint64_t* tcnt[2][2];  // per species, two buffers used by alternate passes
   int tsel[2];           // the buffer the next pass of each species adds into
   uint4* rq[2];
@@ -278,6 +294,8 @@ struct pic_handle {
   int cur[2];
   int pcur[2];  // active pool buffer per species
   int cur_hi;
+  int e_decided;  // the last step decided the next step's electrons (pipelined)
+  int pipeline;   // pipelined electron steps allowed (pic_set_pipeline)
   int measuring;
   int field_fixed_set;
   pic::PartLaunch launch[2];  // [species]

@@ -216,6 +216,9 @@ class Discharge:
         check(self.L.pic_set_launch(self.h, int(decide_wg_per_cu), int(emit_wg_per_cu)),
               "pic_set_launch")
 
+    def set_pipeline(self, on=True):
+        check(self.L.pic_set_pipeline(self.h, 1 if on else 0), "pic_set_pipeline")
+
     def tune(self, steps_per_trial=100):
         """Measures the particle kernels' launch shapes on this discharge
         (advancing it) and keeps the fastest; returns (decide, emit)

@@ -355,6 +355,12 @@ def test_timing_levels():
     d.step(10)
     t = d.get_timing(reset=True)
     assert t["e_decide"][1] == 10 and t["e_emit"][1] == 10 and t["i_decide"][1] == 2
+    # pipelined steps have no decide pass of their own
+    d.set_pipeline(True)
+    d.step(10)
+    t = d.get_timing(reset=True)
+    assert 1 <= t["e_decide"][1] < 10 and t["e_emit"][1] == 10 and t["i_decide"][1] == 2
+    d.set_pipeline(False)
     assert all(v[0] > 0 for k, v in t.items() if v[1])
     d.timing(0)
     d.step(5)
