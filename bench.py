@@ -61,6 +61,15 @@ PASS_TRAFFIC_SOURCE = ("constant per electron particle-step from "
                        "profiles/particle_pass_c3_large_lowp_hbm_traffic.md (rocprofv3 FETCH_SIZE x2 + "
                        "WRITE_SIZE over 20 steps after two RF cycles), times this window's particles")
 
+# the kernels the electron pass timer covers (per step, in launch order)
+PASS_KERNELS = ("electron particle pass: k_decide<0> + k_emit<0> + k_tail<0> (its queued slots, "
+                "overlapped with the next step's field); k_rare<0> instead of k_tail on ion steps")
+PASS_KERNELS_PIPELINED = (
+    "electron particle pass, pipelined: k_field_cand (next step's field and candidacy bits) + "
+    "k_emit_decide<0> (this step's emit, the next step's decisions, this step's queued slots); "
+    "on ion steps k_emit<0> + k_rare<0>, on the step after one k_decide<0> + k_field_cand + "
+    "k_emit_decide<0>")
+
 DESCRIPTIONS = {
     "c3_large_lowp": ("gap 6.7 cm, 2048 cells, dt=T_RF/8000, 13.56 MHz, 500 V, 2 Pa, gamma 0.2, R 0.5, "
                       "4M e + 4M Ar+ fp64, ions sub-cycled x10, synthetic argon cross sections"),
@@ -290,6 +299,8 @@ def main():
                          "1000 RF cycles, training on 40, 6 warm runs of 1000 cycles), full (about 10 "
                          "GPU-minutes: 112 cold runs of 2000 cycles, 16 warm runs of 2000) or none")
     ap.add_argument("--no-c1", action="store_true", help="skip the small discharge in full")
+    ap.add_argument("--pipeline", choices=("on", "off"), default="on",
+                    help="pipelined electron steps (pic_set_pipeline) for the timed workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs one discharge on one GPU; --gpus {args.gpus} is not supported "
@@ -324,6 +335,7 @@ def main():
     d = Discharge(p, xs, "cuda:0")
     for sp in (0, 1):
         d.set_state(sp, *init[sp], step=0)
+    d.set_pipeline(args.pipeline == "on")
     chunk = max(1, nt // 4)
     done = 0
     while done < warmup:
@@ -407,9 +419,7 @@ def main():
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                     "traffic_unit": "HBM bytes per launch", "traffic_source": PASS_TRAFFIC_SOURCE,
-                    "kernel": ("electron particle pass: k_decide<0> + k_emit<0> + k_tail<0> "
-                               "(its queued slots, overlapped with the next step's field); "
-                               "k_rare<0> instead of k_tail on ion steps"),
+                    "kernel": (PASS_KERNELS_PIPELINED if args.pipeline == "on" else PASS_KERNELS),
                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
                     "particles_per_launch": pe_w / en, "window_steps": steps}
 
@@ -432,6 +442,9 @@ def main():
             "particle_steps_e": pe, "particle_steps_i": pi,
             "n_cells": p["n_cells"], "steps_per_cycle": nt, "ion_subcycle": p["ion_subcycle"],
             "sort_interval": p["sort_interval"], "parallelism": "single GPU",
+            "pipeline": args.pipeline,
+            "collision_candidates": int((c1[7] - c0[7]) + (c1[11] - c0[11])),
+            "beyond_table": int(c1[15] - c0[15]),
         },
         "roofline": roof,
         "kernels": kernels,

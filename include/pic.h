@@ -348,7 +348,7 @@ void pic_batch_free(pic_batch* b);
  * the tiles and every per-slot decision are the same for any grid. */
 int pic_set_launch(pic_handle* h, int decide_wg_per_cu, int emit_wg_per_cu);
 
-/* Pipelined electron steps on (1) or off (0, the default). On, within one
+/* Pipelined electron steps on (1, the default) or off (0). On, within one
  * pic_step call the electron emit of a step also takes the next step's
  * electron decisions (push, candidacy, walls, collision process, deposit),
  * so that step has no decide pass of its own; this applies to steps that

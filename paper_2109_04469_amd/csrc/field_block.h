@@ -57,15 +57,54 @@ __device__ __forceinline__ double to_double(i128p v) {
   return neg ? -r : r;
 }
 
+// One step of a wave scan with data-parallel lane moves on each 32-bit word
+// of a multi-word integer: the moved value (0 where a lane has no source)
+// added with carries. CTRL, ROW_MASK, BOUND as in wave_incl_scan_dpp.
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ uint32_t dpp_word(uint32_t w) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, CTRL, ROW_MASK, 0xF, BOUND);
+}
+
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ void scan_step64(uint64_t& v) {
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  const uint64_t u = (uint64_t)dpp_word<CTRL, ROW_MASK, BOUND>(lo) |
+                     ((uint64_t)dpp_word<CTRL, ROW_MASK, BOUND>(hi) << 32);
+  v += u;
+}
+
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ void scan_step128(i128p& v) {
+  const uint64_t lo = v.lo, hi = (uint64_t)v.hi;
+  i128p u;
+  u.lo = (uint64_t)dpp_word<CTRL, ROW_MASK, BOUND>((uint32_t)lo) |
+         ((uint64_t)dpp_word<CTRL, ROW_MASK, BOUND>((uint32_t)(lo >> 32)) << 32);
+  u.hi = (int64_t)((uint64_t)dpp_word<CTRL, ROW_MASK, BOUND>((uint32_t)hi) |
+                   ((uint64_t)dpp_word<CTRL, ROW_MASK, BOUND>((uint32_t)(hi >> 32)) << 32));
+  v = add128(v, u);
+}
+
+// Wave-level inclusive scans of 64- and 128-bit integers with lane moves:
+// the same steps as wave_incl_scan_dpp (shifts by 1, 2, 4, 8 inside each
+// row of 16, then the row broadcasts), two's complement sums with carries.
+__device__ __forceinline__ int64_t wave_incl_scan64(int64_t x) {
+  uint64_t v = (uint64_t)x;
+  scan_step64<0x111, 0xF, true>(v);
+  scan_step64<0x112, 0xF, true>(v);
+  scan_step64<0x114, 0xF, true>(v);
+  scan_step64<0x118, 0xF, true>(v);
+  scan_step64<0x142, 0xA, false>(v);
+  scan_step64<0x143, 0xC, false>(v);
+  return (int64_t)v;
+}
+
 __device__ __forceinline__ i128p wave_incl_scan128(i128p v) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    i128p u;
-    u.lo = __shfl_up(v.lo, o, kWave);
-    u.hi = __shfl_up(v.hi, o, kWave);
-    if (lane >= o) v = add128(v, u);
-  }
+  scan_step128<0x111, 0xF, true>(v);
+  scan_step128<0x112, 0xF, true>(v);
+  scan_step128<0x114, 0xF, true>(v);
+  scan_step128<0x118, 0xF, true>(v);
+  scan_step128<0x142, 0xA, false>(v);
+  scan_step128<0x143, 0xC, false>(v);
   return v;
 }
 
@@ -73,13 +112,13 @@ __device__ __forceinline__ i128p wave_incl_scan128(i128p v) {
 __device__ __forceinline__ int64_t block_excl_scan64(int64_t v, int64_t& excl, int64_t* s_wave) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
-  const int64_t inc = wave_incl_scan<long long>((long long)v);
+  const int64_t inc = wave_incl_scan64(v);
   if (lane == kWave - 1) s_wave[wave] = inc;
   __syncthreads();
   if (wave == 0) {
     // exclusive scan of the wave totals by the first wave
     const int64_t t = lane < kFieldWaves ? s_wave[lane] : 0;
-    const int64_t ti = wave_incl_scan<long long>((long long)t);
+    const int64_t ti = wave_incl_scan64(t);
     if (lane < kFieldWaves) s_wave[lane] = ti - t;
     if (lane == kFieldWaves - 1) s_wave[kFieldWaves] = ti;
   }
@@ -129,15 +168,29 @@ __device__ __forceinline__ void field_block(const FieldArgs& a) {
   const int tid = threadIdx.x;
   const int nx = a.nx;
   if (tid == 0) {
+    // stores and non-returning atomics: the first wave does not wait on a
+    // read of the control block
     a.ctl->ncodes[1] = 0;
-    a.ctl->counters[C_STEPS] += 1ull;
-    if (a.measuring) a.ctl->msteps += 1;
+    atomicAdd(&a.ctl->counters[C_STEPS], 1ull);
+    if (a.measuring) atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctl->msteps), 1ull);
   }
-  for (int j = tid; j < nx; j += kFieldThreads) {
+  // every deposit load of this thread in flight before the first use (one
+  // memory round trip instead of one per stride)
+  int64_t dep_e_v[kFieldPer], dep_i_v[kFieldPer];
+#pragma unroll
+  for (int k = 0; k < kFieldPer; ++k) {
+    const int j = tid + k * kFieldThreads;
+    dep_e_v[k] = j < nx ? a.dep_e[j] : 0;
+    dep_i_v[k] = j < nx ? a.dep_i[j] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kFieldPer; ++k) {
+    const int j = tid + k * kFieldThreads;
+    if (j >= nx) continue;
     if (a.zero_a) a.zero_a[j] = 0;
     if (a.zero_b) a.zero_b[j] = 0;
-    const int64_t de = a.dep_e[j];
-    const int64_t di = a.dep_i[j];
+    const int64_t de = dep_e_v[k];
+    const int64_t di = dep_i_v[k];
     const int64_t c = di - de;
     sC[j] = c;
     double r = (double)c * a.qfac32;

@@ -174,11 +174,15 @@ __device__ __forceinline__ void record_arrival(const PartArgs& a, int64_t slot, 
 // pool index unknown to the caller: decide_rare reads it from a.idin
 constexpr uint32_t kNoId = 0xFFFFFFFFu;
 
-template <int SP, bool MEASURE>
+// EAGER: an electron candidate's three cumulative frequencies are read
+// together, not each after the previous comparison (the same values; more
+// registers, one memory round trip instead of up to three). vyz: the
+// particle's v_y, v_z when the caller holds them (else read from the pool).
+template <int SP, bool MEASURE, bool EAGER = false>
 __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long long* s_cnt,
                                             int64_t slot, bool cand, double& x, double& vx,
                                             uint32_t& c, uint32_t& o, uint32_t& b,
-                                            uint32_t pid = kNoId) {
+                                            uint32_t pid = kNoId, const double* vyz = nullptr) {
   const double L = a.L;
   const uint32_t step = a.step;
   bool alive = true;
@@ -230,20 +234,33 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
       // electron candidate: the process at this speed decides whether a
       // second electron and an ion are born
       atomicAdd(&s_cnt[C_E_CAND], 1ull);
-      const uint32_t id = pid != kNoId ? pid : a.idin[slot];
-      const double vy = a.pvy[id], vz = a.pvz[id];
+      double vy, vz;
+      if (vyz) {
+        vy = vyz[0];
+        vz = vyz[1];
+      } else {
+        const uint32_t id = pid != kNoId ? pid : a.idin[slot];
+        vy = a.pvy[id];
+        vz = a.pvz[id];
+      }
       const double g2 = sqrt(vx * vx + vy * vy + vz * vz);
       const double tv = g2 * a.inv_dv;
       const double r = u01(draw(step, (uint32_t)slot, SP, 0, a.seed, a.run).z) * a.numax;
       if (!(tv < (double)(a.ntab - 1))) atomicAdd(&s_cnt[C_BEYOND_TABLE], 1ull);
       uint32_t proc = 1;
-      if (r < cum_nu(a.cum, a.ntab, 0, tv)) {
+      double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+      if (EAGER) {
+        n0 = cum_nu(a.cum, a.ntab, 0, tv);
+        n1 = cum_nu(a.cum, a.ntab, 1, tv);
+        n2 = cum_nu(a.cum, a.ntab, 2, tv);
+      }
+      if (r < (EAGER ? n0 : cum_nu(a.cum, a.ntab, 0, tv))) {
         proc = 2;
         atomicAdd(&s_cnt[C_E_ELASTIC], 1ull);
-      } else if (r < cum_nu(a.cum, a.ntab, 1, tv)) {
+      } else if (r < (EAGER ? n1 : cum_nu(a.cum, a.ntab, 1, tv))) {
         proc = 3;
         atomicAdd(&s_cnt[C_E_EXC], 1ull);
-      } else if (r < cum_nu(a.cum, a.ntab, 2, tv)) {
+      } else if (r < (EAGER ? n2 : cum_nu(a.cum, a.ntab, 2, tv))) {
         proc = 4;
         b = 1;
         mul = 2;
@@ -573,25 +590,22 @@ __device__ __forceinline__ void reload(const PartArgs& a, const double* E, int64
 // Electron decision of step b.step for the single slot `slot` of that
 // step's arrays, holding x, vx (the state the previous step left) and pool
 // entry id: field at the particle from E (b's field, in LDS or global
-// memory), the push, the candidacy draw (word slot mod 4 of the block
-// (step, slot / 4, 4, 0)), and for the few slots that left the gap or are
-// candidates the wall and collision decisions. The same arithmetic as
+// memory), the push, and for the few slots that left the gap or are
+// candidates (cand: the slot's candidacy bit, Philox word slot mod 4 of
+// the block (step, slot / 4, 4, 0) below the threshold, drawn with the
+// step's field) the wall and collision decisions. The same arithmetic as
 // decide_tiles, one slot at a time. x and vx become the pushed state
 // (mirrored when reflected); c, o, bb: decision code, own outputs and
 // births of the slot in step b.step.
 __device__ __forceinline__ void decide_one(const PartArgs& b, const double* E, int64_t slot,
                                            double& x, double& vx, uint32_t id,
-                                           unsigned long long* s_cnt, uint32_t& c, uint32_t& o,
-                                           uint32_t& bb) {
+                                           unsigned long long* s_cnt, bool cand, uint32_t& c,
+                                           uint32_t& o, uint32_t& bb) {
   int j;
   double f;
   int64_t w1;
   cell_of(x, b.inv_dx, b.nx, j, f, w1);
   push(E, j, f, b.acc, b.dts, x, vx);
-  const uint4 r = draw(b.step, (uint32_t)(slot >> 2), 0, 4, b.seed, b.run);
-  const int q = (int)(slot & 3);
-  const uint32_t w = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
-  const bool cand = (uint64_t)w < (b.no_coll ? 0ull : b.pcoll_thr);
   c = kCodePushed;
   o = 1u;
   bb = 0u;
@@ -611,6 +625,8 @@ constexpr int kStrideLoads = 8;
 
 // pairs of consecutive slots per lane and tile in k_emit
 constexpr int kEPairs = kPPT / 2;
+// candidacy bit words covering the outputs of one tile (at most 2 kTile)
+constexpr int kCandWords = 2 * kTile / 32 + 1;
 static_assert(kPPT % 2 == 0, "k_emit takes pairs of slots");
 
 // Counts of a particle pass with no slots.
@@ -647,7 +663,9 @@ __device__ __forceinline__ void emit_empty(DevCtl* ctl, int par) {
 // (decide_one with b's field in sE): the output slot receives the pushed
 // state of that step, its decision code goes to b.codes, its deposit to the
 // LDS histogram sH (flushed by the caller over [jlo, jhi]), its outcome to
-// the next pass's tile totals b.tcnt, its events to s_cnt.
+// the next pass's tile totals b.tcnt, its events to s_cnt. MODE 3: as MODE 2
+// on an input that holds the state before the push, which is repeated first
+// with a's field (in sE0).
 template <int SP, int STAGE_PER, int MODE = 0>
 __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, int t_step,
                                            int ntiles, int64_t n_tot, int64_t bbase, double* sE,
@@ -658,8 +676,12 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
                                            const PartArgs* b = nullptr,
                                            unsigned long long* sH = nullptr,
                                            unsigned long long* s_cnt = nullptr,
-                                           int* jlo_out = nullptr, int* jhi_out = nullptr) {
-  static_assert(MODE != 2 || SP == 0, "only electron passes decide the next step");
+                                           int* jlo_out = nullptr, int* jhi_out = nullptr,
+                                           uint32_t (*s_cand)[kCandWords] = nullptr,
+                                           uint32_t* s_dcnt = nullptr, double* sE0 = nullptr,
+                                           int64_t* rq_range = nullptr) {
+  constexpr bool FUSE = MODE >= 2;
+  static_assert(!FUSE || SP == 0, "only electron passes decide the next step");
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = tid / kWave;
@@ -678,7 +700,8 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       v[u] = t < t0 ? a.tcnt[t] : 0ull;
     }
     if (!staged) {
-      if (MODE != 1) stage_field<kBlock, STAGE_PER>(sE, MODE == 2 ? b->E : a.E, a.nx);
+      if (MODE != 1) stage_field<kBlock, STAGE_PER>(sE, FUSE ? b->E : a.E, a.nx);
+      if (MODE == 3) stage_field<kBlock, STAGE_PER>(sE0, a.E, a.nx);
       staged = true;
     }
 #pragma unroll
@@ -688,7 +711,8 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       pr += v[u] >> 32;
     }
   }
-  if (!staged && MODE != 1) stage_field<kBlock, STAGE_PER>(sE, MODE == 2 ? b->E : a.E, a.nx);
+  if (!staged && MODE != 1) stage_field<kBlock, STAGE_PER>(sE, FUSE ? b->E : a.E, a.nx);
+  if (!staged && MODE == 3) stage_field<kBlock, STAGE_PER>(sE0, a.E, a.nx);
   po = wave_sum<unsigned long long>(po);
   pb = wave_sum<unsigned long long>(pb);
   pr = wave_sum<unsigned long long>(pr);
@@ -705,7 +729,11 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
     prefR += (int64_t)s_red[2][w];
   }
 
-  // MODE 2: this lane's deposit run (cell jr, weights of nodes jr, jr + 1)
+  // MODE 2: this lane's deposit run (cell jr, weights of nodes jr, jr + 1);
+  // the workgroup's first output slot (its deferred list starts there: the
+  // workgroup defers at most its own outputs) and first queued slot
+  const int64_t wg_out0 = prefO;
+  const int64_t wg_rq0 = prefR;
   int jr = -1, jlo = INT_MAX, jhi = -1;
   unsigned long long h0 = 0ull, h1 = 0ull;
   for (int t = t0; t < t1; t += t_step) {
@@ -726,6 +754,15 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
           nsr += (uint32_t)(v >> 32);
         }
       }
+    }
+    if (FUSE) {
+      // the next step's candidacy bits of this tile's outputs (at most
+      // 2 kTile slots from the tile's first output), into LDS with the loads
+      // of the tile
+      const int64_t w0 = prefO >> 5;
+      const int64_t nwords = (a.cap + 31) / 32 + 1;
+      for (int i = tid; i < kCandWords; i += kBlock)
+        s_cand[p][i] = w0 + i < nwords ? b->cand[w0 + i] : 0u;
     }
     // pairs of consecutive slots per lane: 16-byte loads of x and v_x, an
     // 8-byte load of the two pool indices, one 2-byte load of the codes;
@@ -809,10 +846,12 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
     const int64_t tA = prefO / kTile;
     uint32_t nt[3] = {0u, 0u, 0u};
 
+
 #pragma unroll
     for (int k = 0; k < kEPairs; ++k) {
       uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)(si - sv), k * nw + wv) + loc[k];
       uint32_t roff = (uint32_t)__builtin_amdgcn_readlane((int)(sri - sr), k * nw + wv) + rloc[k];
+      uint32_t dq_slot[2] = {0xFFFFFFFFu, 0xFFFFFFFFu};
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int q = 2 * k + h;
@@ -832,19 +871,24 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
           const int64_t dest = prefO + (int64_t)(off & 0xFFFFu);
           double x = px[q], vx = pvx[q];
           if (MODE == 0) repush(a, sE, c, x, vx);
-          if (MODE == 2 && dest < a.cap) {
-            uint32_t c2, o2, b2;
-            decide_one(*b, sE, dest, x, vx, pid[q], s_cnt, c2, o2, b2);
-            b->codes[dest] = (uint8_t)c2;
-            const uint32_t rel = (uint32_t)(dest / kTile - tA);
-            const uint32_t word = o2 | (b2 << 11) | ((outcome<0>(c2).rare ? 1u : 0u) << 22);
-            nt[0] += rel == 0u ? word : 0u;
-            nt[1] += rel == 1u ? word : 0u;
-            nt[2] += rel == 2u ? word : 0u;
-            if (o2) {
-              int jd;
-              double fd;
-              int64_t w1;
+          if (MODE == 3) repush(a, sE0, c, x, vx);
+          bool defer = false;
+          if (FUSE && dest < a.cap) {
+            // the next step's push; a slot that leaves the gap or is a
+            // collision candidate is decided after this workgroup's tiles
+            int jd;
+            double fd;
+            int64_t w1;
+            cell_of(x, b->inv_dx, b->nx, jd, fd, w1);
+            push(sE, jd, fd, b->acc, b->dts, x, vx);
+            const uint32_t cw = s_cand[p][(int)((dest >> 5) - (prefO >> 5))];
+            defer = ((cw >> (dest & 31)) & 1u) != 0 || !(x >= 0.0 && x <= b->L) || !isfinite(vx);
+            if (!defer) {
+              b->codes[dest] = (uint8_t)kCodePushed;
+              const uint32_t rel = (uint32_t)(dest / kTile - tA);
+              nt[0] += rel == 0u ? 1u : 0u;
+              nt[1] += rel == 1u ? 1u : 0u;
+              nt[2] += rel == 2u ? 1u : 0u;
               cell_of(x, b->inv_dx, b->nx, jd, fd, w1);
               if (jd != jr) {
                 if (jr >= 0) {
@@ -856,16 +900,32 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
                 jlo = min(jlo, jd);
                 jhi = max(jhi, jd + 1);
               }
-              h0 += (unsigned long long)o2 * (unsigned long long)(kOne32 - w1);
-              h1 += (unsigned long long)o2 * (unsigned long long)w1;
+              h0 += (unsigned long long)(kOne32 - w1);
+              h1 += (unsigned long long)w1;
             }
           }
           if (dest < a.cap) store3(a, dest, x, vx, pid[q]);
+          if (FUSE) dq_slot[h] = defer ? (uint32_t)dest : 0xFFFFFFFFu;
         }
         if (in) off += oc.own | (oc.birth << 16);
       }
+      if (FUSE) {
+        // this row's deferred slots appended to the workgroup's list (an
+        // LDS counter, one atomic per wave, only for rows that have any)
+        const uint32_t nd = (dq_slot[0] != 0xFFFFFFFFu ? 1u : 0u) + (dq_slot[1] != 0xFFFFFFFFu ? 1u : 0u);
+        if (__ballot(nd != 0u)) {
+          const uint32_t inc = wave_incl_scan_dpp(nd);
+          const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+          uint32_t base = 0u;
+          if (lane == 0) base = atomicAdd(s_dcnt, tot);
+          base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+          int64_t idx = wg_out0 + (int64_t)(base + inc - nd);
+          if (dq_slot[0] != 0xFFFFFFFFu) b->dq[idx++] = dq_slot[0];
+          if (dq_slot[1] != 0xFFFFFFFFu) b->dq[idx] = dq_slot[1];
+        }
+      }
     }
-    if (MODE == 2) {
+    if (FUSE) {
       // this wave's share of the next pass's tile totals (per wave at most
       // 2 * kPPT * 64 outputs, kPPT * 64 births and queued slots: 11, 11
       // and 10 bits), widened to the totals' layout
@@ -913,12 +973,16 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       // pool (the new electron and the new ion), an emission one electron
       // entry; k_rare fills them from these bases
       const int other = 1 - SP;
-      ctl->pbase[SP] = ctl->pool_n[SP];
-      ctl->pbase[other] = ctl->pool_n[other];
+      if (!FUSE) {
+        // (a fused pass reads them while this runs: the field kernel before
+        // it has set them)
+        ctl->pbase[SP] = ctl->pool_n[SP];
+        ctl->pbase[other] = ctl->pool_n[other];
+      }
       if (SP == 0) ctl->pool_n[SP] += prefB;
       ctl->pool_n[other] += prefB;
       if (ctl->pool_n[SP] > a.pcap || ctl->pool_n[other] > a.bpcap) latch_error(ctl, kErrCapacity);
-      if (MODE == 2) {
+      if (FUSE) {
         // the next step pushes every output of this one
         const int64_t np = prefO < a.cap ? prefO : a.cap;
         if (b->record) ctl->ncodes[SP] = np;
@@ -926,7 +990,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
       }
     }
   }
-  if (MODE == 2) {
+  if (FUSE) {
     if (jr >= 0) {
       atomicAdd(&sH[jr], h0);
       atomicAdd(&sH[jr + 1], h1);
@@ -935,6 +999,11 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
     *jhi_out = jhi;
   }
   __syncthreads();  // the field and the totals may be reused by the caller
+  if (FUSE && rq_range) {
+    rq_range[0] = wg_rq0;
+    rq_range[1] = prefR;
+    rq_range[2] = wg_out0;
+  }
 }
 
 template <int SP, int MODE>
@@ -949,6 +1018,12 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   const int tid = threadIdx.x;
   DevCtl* ctl = a.ctl;
   const int par = a.parity;
+  // MODE 1 follows a fused pass that decided this step; the decide pass that
+  // would have zeroed the next pass's totals buffer did not run
+  if (MODE == 1)
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < a.max_tiles;
+         i += (int64_t)gridDim.x * kBlock)
+      a.tcnt_next[i] = 0ull;
 
   int64_t n_push = uniform64(SP == 0 ? ctl->n_e[par] : ctl->n_i[par]);
   int64_t n_tot = SP == 0 ? n_push : n_push + uniform64(ctl->i_births);
@@ -978,70 +1053,6 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
 
   emit_tiles<SP, (kMaxNx + kBlock - 1) / kBlock, MODE>(a, t0, t1, t_step, ntiles, n_tot, bbase,
                                                         sE, s_wtot, s_wr, s_ps, s_red);
-}
-
-// The electron emit of pass a fused with the electron decisions of the next
-// step b (emit_tiles MODE 2): a's input holds pushed, decided state; the
-// outputs that need no queued work leave pushed and decided for b, so the
-// next step has no decide pass of its own. Contiguous runs of tiles per
-// workgroup (as k_emit for electrons); b's field in LDS with the deposit
-// histogram, flushed once per workgroup.
-__global__ __launch_bounds__(kBlock) void k_emit_decide(PartArgs a, PartArgs b) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int nx = a.nx;
-  double* sE = reinterpret_cast<double*>(smem);
-  unsigned long long* sH = reinterpret_cast<unsigned long long*>(sE + nx);
-  __shared__ uint32_t s_wtot[2][kEPairs][kBlock / kWave];
-  __shared__ uint32_t s_wr[2][kEPairs][kBlock / kWave];
-  __shared__ uint32_t s_ps[2][3][kBlock / kWave];
-  __shared__ uint64_t s_red[3][kBlock / kWave];
-  __shared__ unsigned long long s_cnt[NCOUNTERS];
-  __shared__ int s_lo, s_hi;
-
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  DevCtl* ctl = a.ctl;
-  const int par = a.parity;
-  for (int j = tid; j < nx; j += kBlock) sH[j] = 0ull;
-  if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
-  if (tid == 0) {
-    s_lo = INT_MAX;
-    s_hi = -1;
-  }
-
-  int64_t n_tot = uniform64(ctl->n_e[par]);
-  if (n_tot > a.cap) n_tot = a.cap;  // the decide has latched the error
-  const int64_t bbase = uniform64(ctl->n_i[par]);
-  const int ntiles = uniform32((int)((n_tot + kTile - 1) / kTile));
-  if (ntiles == 0) {
-    if (blockIdx.x == 0 && tid == 0) {
-      emit_empty<0>(ctl, par);
-      if (b.record) ctl->ncodes[0] = 0;
-    }
-    return;
-  }
-  const int t0 = uniform32((int)((int64_t)ntiles * blockIdx.x / gridDim.x));
-  const int t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
-  __syncthreads();  // sH, s_cnt, s_lo, s_hi set
-  if (t0 >= t1) return;
-
-  int jlo = INT_MAX, jhi = -1;
-  emit_tiles<0, (kMaxNx + kBlock - 1) / kBlock, 2>(a, t0, t1, 1, ntiles, n_tot, bbase, sE, s_wtot,
-                                                   s_wr, s_ps, s_red, &b, sH, s_cnt, &jlo, &jhi);
-  // one flush of the deposit range of this workgroup's outputs
-  jlo = wave_min(jlo);
-  jhi = wave_max(jhi);
-  if (lane == 0) {
-    atomicMin(&s_lo, jlo);
-    atomicMax(&s_hi, jhi);
-  }
-  __syncthreads();
-  const int lo = s_lo, hi = s_hi;
-  for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += kBlock) {
-    const unsigned long long v = sH[j];
-    if (v) atomicAdd(&b.dep_own[j], v);
-  }
-  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1102,11 +1113,26 @@ __device__ __forceinline__ void deposit_global_n(unsigned long long* dep, double
 // time: decide_one with b's field from global memory, the decision code,
 // the next pass's tile totals and the deposit with global atomics, and the
 // pushed state stored at the slot.
+// ef[2]: b's field at the two nodes of x's cell and cw the candidacy word of
+// dest, loaded by the caller ahead of the collision kinematics.
 __device__ __forceinline__ void next_step_output(const PartArgs& a, const PartArgs& b,
                                                  unsigned long long* s_cnt, int64_t dest,
-                                                 double x, double vx, uint32_t id) {
-  uint32_t c2, o2, b2;
-  decide_one(b, b.E, dest, x, vx, id, s_cnt, c2, o2, b2);
+                                                 double x, double vx, double vy, double vz,
+                                                 uint32_t id, const double* ef, uint32_t cw) {
+  uint32_t c2 = kCodePushed, o2 = 1u, b2 = 0u;
+  int j;
+  double f;
+  int64_t w1;
+  cell_of(x, b.inv_dx, b.nx, j, f, w1);
+  // push() on the prefetched node values: the same operations and operands
+  const double Ep = (1.0 - f) * ef[0] + f * ef[1];
+  vx = vx + b.acc * Ep;
+  x = x + vx * b.dts;
+  const bool cand = ((cw >> (dest & 31)) & 1u) != 0;
+  if (cand || !(x >= 0.0 && x <= b.L) || !isfinite(vx)) {
+    const double vyz[2] = {vy, vz};
+    decide_rare<0, false, true>(b, s_cnt, dest, cand, x, vx, c2, o2, b2, id, vyz);
+  }
   b.codes[dest] = (uint8_t)c2;
   atomicAdd(&b.tcnt[dest / kTile], totals_word(c2, o2, b2));
   if (o2) deposit_global_n(b.dep_own, x, b.inv_dx, b.nx, o2);
@@ -1122,20 +1148,39 @@ template <int SP, bool VAR, bool PUSHED = false, bool FUSED = false>
 __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long* s_cnt,
                                           int64_t slot, uint32_t c, int64_t dest, int64_t r,
                                           int64_t bbase, const PartArgs* nb = nullptr) {
-  static_assert(!FUSED || (PUSHED && SP == 0), "only pushed electron slots are fused");
+  static_assert(!FUSED || SP == 0, "only electron slots are fused");
   const uint32_t step = a.step;
   const double L = a.L;
   const int64_t bdest = bbase + r;
   double x, vx, vy, vz;
   uint32_t id;
+  // FUSED: the next step's field at the particle's cell (collisions do not
+  // move it; an ionization electron is born there) and the candidacy words
+  // of its output slots, loaded with the particle
+  double ef[2] = {0.0, 0.0};
+  uint32_t cw0 = 0u, cw1 = 0u;
   if (PUSHED) {
     x = a.xin[slot];
     vx = a.vxin[slot];
     id = a.idin[slot];
+    if (FUSED) {
+      if (dest < a.cap) cw0 = nb->cand[dest >> 5];
+      if (dest + 1 < a.cap) cw1 = nb->cand[(dest + 1) >> 5];
+      const int jn = cell_key(x, nb->inv_dx, nb->nx);
+      ef[0] = nb->E[jn];
+      ef[1] = nb->E[jn + 1];
+    }
     vy = a.pvy[id];
     vz = a.pvz[id];
   } else {
     reload(a, a.E, slot, c, x, vx, id, vy, vz);
+    if (FUSED) {
+      if (dest < a.cap) cw0 = nb->cand[dest >> 5];
+      if (dest + 1 < a.cap) cw1 = nb->cand[(dest + 1) >> 5];
+      const int jn = cell_key(x, nb->inv_dx, nb->nx);
+      ef[0] = nb->E[jn];
+      ef[1] = nb->E[jn + 1];
+    }
   }
   const Outcome oc = outcome<SP>(c);
   bool child = false;
@@ -1251,13 +1296,13 @@ __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long*
       // pool entries first: the next step's decision reads them
       a.pvy[id] = vy;
       a.pvz[id] = vz;
-      if (dest < a.cap) next_step_output(a, *nb, s_cnt, dest, x, vx, id);
+      if (dest < a.cap) next_step_output(a, *nb, s_cnt, dest, x, vx, vy, vz, id, ef, cw0);
       if (child) {
         const int64_t cid = a.ctl->pbase[SP] + r;
         if (dest + 1 < a.cap && cid < a.pcap) {
           a.pvy[cid] = cvy;
           a.pvz[cid] = cvz;
-          next_step_output(a, *nb, s_cnt, dest + 1, x, cvx, (uint32_t)cid);
+          next_step_output(a, *nb, s_cnt, dest + 1, x, cvx, cvy, cvz, (uint32_t)cid, ef, cw1);
         }
       }
     } else {
@@ -1305,28 +1350,126 @@ __global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
 }
 
-// The queued slots of electron pass a (pushed input), each output then
-// decided for the next step b; and a's tile totals, read by a's emit, are
-// zeroed for the pass after b, which adds into the same buffer.
-template <bool VAR>
-__global__ __launch_bounds__(kBlock) void k_tail2(PartArgs a, PartArgs b) {
+// ---------------------------------------------------------------------------
+// The electron emit of pass a fused with the electron decisions of the next
+// step b (emit_tiles MODE 2): a's input holds pushed, decided state; the
+// outputs that need no queued work leave pushed and decided for b, so the
+// next step has no decide pass of its own. Contiguous runs of tiles per
+// workgroup (as k_emit for electrons); b's field in LDS with the deposit
+// histogram, flushed once per workgroup.
+// An output at slot dest that the fused emit pushed for step b but left
+// undecided (it left the gap or is a collision candidate): the wall and
+// collision decisions, the decision code, the tile totals and the deposit,
+// and the (possibly mirrored) pushed state stored back.
+__device__ __forceinline__ void deferred_decision(const PartArgs& a, const PartArgs& b,
+                                                  unsigned long long* s_cnt, int64_t dest) {
+  double x = a.xout[dest], vx = a.vxout[dest];
+  const uint32_t id = a.idout[dest];
+  const bool cand = ((b.cand[dest >> 5] >> (dest & 31)) & 1u) != 0;
+  uint32_t c = kCodePushed, o = 1u, bb = 0u;
+  double vyz[2] = {0.0, 0.0};
+  if (cand) {
+    vyz[0] = a.pvy[id];
+    vyz[1] = a.pvz[id];
+  }
+  decide_rare<0, false, true>(b, s_cnt, dest, cand, x, vx, c, o, bb, id, vyz);
+  b.codes[dest] = (uint8_t)c;
+  atomicAdd(&b.tcnt[dest / kTile], totals_word(c, o, bb));
+  if (o) deposit_global_n(b.dep_own, x, b.inv_dx, b.nx, o);
+  a.xout[dest] = x;
+  a.vxout[dest] = vx;
+}
+
+// MODE 2: a's input holds the pushed, decided state; MODE 3: the state
+// before the push (the first pipelined step after a plain decide), pushed
+// again here with a's field.
+#ifndef EMIT_DECIDE_MIN_WAVES
+#define EMIT_DECIDE_MIN_WAVES 1  // waves per SIMD the register budget must allow
+#endif
+//
+// Each workgroup ends with the rare work of its own tiles: its queued slots
+// of pass a (collision kinematics, the outputs then decided for b) and the
+// outputs it deferred, one item per thread; these are chains of dependent
+// loads that other workgroups' streaming hides. VAR: the method-variant
+// kinematics compiled in.
+template <int MODE, bool VAR>
+__global__ __launch_bounds__(kBlock, EMIT_DECIDE_MIN_WAVES) void k_emit_decide(PartArgs a, PartArgs b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nx = a.nx;
+  double* sE = reinterpret_cast<double*>(smem);
+  unsigned long long* sH = reinterpret_cast<unsigned long long*>(sE + nx);
+  double* sE0 = MODE == 3 ? reinterpret_cast<double*>(sH + nx) : nullptr;
+  __shared__ uint32_t s_wtot[2][kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_wr[2][kEPairs][kBlock / kWave];
+  __shared__ uint32_t s_ps[2][3][kBlock / kWave];
+  __shared__ uint64_t s_red[3][kBlock / kWave];
   __shared__ unsigned long long s_cnt[NCOUNTERS];
+  __shared__ int s_lo, s_hi;
+  __shared__ uint32_t s_cand[2][kCandWords];
+  __shared__ uint32_t s_dcnt[2];
+
   const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  DevCtl* ctl = a.ctl;
+  const int par = a.parity;
+  for (int j = tid; j < nx; j += kBlock) sH[j] = 0ull;
   if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + tid; i < a.max_tiles;
-       i += (int64_t)gridDim.x * kBlock)
-    a.tcnt[i] = 0ull;
-  __syncthreads();
-  const int64_t n = a.ctl->n_rare[0];
-  const int64_t bbase = a.ctl->n_i[a.parity];
-  const int64_t nblk = gridDim.x;
-  for (int64_t i = (int64_t)blockIdx.x + nblk * tid; i < n; i += nblk * kBlock) {
-    const uint4 q = a.rq[i];
-    rare_slot<0, VAR, true, true>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase,
-                                  &b);
+  if (tid == 0) {
+    s_lo = INT_MAX;
+    s_hi = -1;
+    s_dcnt[0] = s_dcnt[1] = 0u;
+  }
+
+  int64_t n_tot = uniform64(ctl->n_e[par]);
+  if (n_tot > a.cap) n_tot = a.cap;  // the decide has latched the error
+  const int64_t bbase = uniform64(ctl->n_i[par]);
+  const int ntiles = uniform32((int)((n_tot + kTile - 1) / kTile));
+  if (ntiles == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
+      emit_empty<0>(ctl, par);
+      if (b.record) ctl->ncodes[0] = 0;
+    }
+    return;
+  }
+  const int t0 = uniform32((int)((int64_t)ntiles * blockIdx.x / gridDim.x));
+  const int t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
+  __syncthreads();  // sH, s_cnt, s_lo, s_hi set
+  if (t0 >= t1) return;
+
+  int jlo = INT_MAX, jhi = -1;
+  int64_t rq_range[3];
+  emit_tiles<0, (kMaxNx + kBlock - 1) / kBlock, MODE>(a, t0, t1, 1, ntiles, n_tot, bbase, sE,
+                                                      s_wtot, s_wr, s_ps, s_red, &b, sH, s_cnt,
+                                                      &jlo, &jhi, s_cand, s_dcnt, sE0, rq_range);
+  // one flush of the deposit range of this workgroup's outputs
+  jlo = wave_min(jlo);
+  jhi = wave_max(jhi);
+  if (lane == 0) {
+    atomicMin(&s_lo, jlo);
+    atomicMax(&s_hi, jhi);
   }
   __syncthreads();
-  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
+  const int lo = s_lo, hi = s_hi;
+  for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += kBlock) {
+    const unsigned long long v = sH[j];
+    if (v) atomicAdd(&b.dep_own[j], v);
+  }
+  // this workgroup's queued slots and deferred decisions
+  const int64_t q0 = uniform64(rq_range[0]);
+  const int64_t nq = uniform64(rq_range[1]) - q0;
+  const int64_t out0 = uniform64(rq_range[2]);
+  const int64_t nd = (int64_t)s_dcnt[0];
+  // queued slots from the first thread up, deferred outputs from the last
+  // thread down: the two chains sit in different waves while they fit
+  for (int64_t i = tid; i < nq; i += kBlock) {
+    const uint4 q = a.rq[q0 + i];
+    rare_slot<0, VAR, MODE == 2, true>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w,
+                                       bbase, &b);
+  }
+  for (int64_t i = kBlock - 1 - tid; i < nd; i += kBlock)
+    deferred_decision(a, b, s_cnt, (int64_t)a.dq[out0 + i]);
+  __syncthreads();
+  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1628,8 +1771,11 @@ PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, in
   c.grid_emit = clamp_grid((int64_t)bpc * num_cu, max_tiles);
   c.bpc_emit = bpc;
   c.lds_emit_decide = emit_decide_lds(nx);
-  c.bpc_emit_decide = species == 0 ? blocks_per_cu(k_emit_decide, c.lds_emit_decide) : 1;
+  c.bpc_emit_decide = species == 0 ? blocks_per_cu(k_emit_decide<2, false>, c.lds_emit_decide) : 1;
   c.grid_emit_decide = clamp_grid((int64_t)c.bpc_emit_decide * num_cu, max_tiles);
+  c.bpc_emit_decide3 =
+      species == 0 ? blocks_per_cu(k_emit_decide<3, false>, c.lds_emit_decide + (size_t)nx * 8) : 1;
+  c.grid_emit_decide3 = clamp_grid((int64_t)c.bpc_emit_decide3 * num_cu, max_tiles);
   c.grid_rare = num_cu * 2;
   c.max_tiles = max_tiles;
   return c;
@@ -1644,6 +1790,8 @@ void particle_launch_set(PartLaunch& c, int num_cu, int kd, int ke) {
   c.grid_emit = clamp_grid((int64_t)k * num_cu, c.max_tiles);
   const int k2 = ke < 1 ? 1 : (ke > c.bpc_emit_decide ? c.bpc_emit_decide : ke);
   c.grid_emit_decide = clamp_grid((int64_t)k2 * num_cu, c.max_tiles);
+  const int k3 = ke < 1 ? 1 : (ke > c.bpc_emit_decide3 ? c.bpc_emit_decide3 : ke);
+  c.grid_emit_decide3 = clamp_grid((int64_t)k3 * num_cu, c.max_tiles);
 }
 
 hipError_t launch_particle_kernel(int kernel, int species, bool measure, const PartArgs& a,
@@ -1690,20 +1838,21 @@ hipError_t launch_particle_kernel(int kernel, int species, bool measure, const P
 }
 
 hipError_t launch_emit_decide(const PartArgs& a, const PartArgs& b, const PartLaunch& c,
-                              hipStream_t s) {
+                              hipStream_t s, bool pushed) {
   if (a.nx > kMaxNx || a.nx != b.nx) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_emit_decide, dim3(c.grid_emit_decide), dim3(kBlock), c.lds_emit_decide, s, a,
-                     b);
+  const dim3 g2(c.grid_emit_decide), g3(c.grid_emit_decide3), t(kBlock);
+  const size_t l2 = c.lds_emit_decide, l3 = c.lds_emit_decide + (size_t)a.nx * 8;
+  if (pushed && a.model)
+    hipLaunchKernelGGL((k_emit_decide<2, true>), g2, t, l2, s, a, b);
+  else if (pushed)
+    hipLaunchKernelGGL((k_emit_decide<2, false>), g2, t, l2, s, a, b);
+  else if (a.model)
+    hipLaunchKernelGGL((k_emit_decide<3, true>), g3, t, l3, s, a, b);
+  else
+    hipLaunchKernelGGL((k_emit_decide<3, false>), g3, t, l3, s, a, b);
   return hipGetLastError();
 }
 
-hipError_t launch_tail2(const PartArgs& a, const PartArgs& b, const PartLaunch& c, hipStream_t s) {
-  if (a.model)
-    hipLaunchKernelGGL((k_tail2<true>), dim3(c.grid_rare), dim3(kBlock), 0, s, a, b);
-  else
-    hipLaunchKernelGGL((k_tail2<false>), dim3(c.grid_rare), dim3(kBlock), 0, s, a, b);
-  return hipGetLastError();
-}
 
 BatchLaunch batch_launch_config(int nx_max, int nbins_max, int num_cu, const int64_t max_tiles[2]) {
   BatchLaunch c{};

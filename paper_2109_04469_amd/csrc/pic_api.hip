@@ -48,7 +48,7 @@ double fedf_ion_emax(double rf_voltage_v) {
 
 struct Layout {
   size_t ctl, part[2][2][2], pid[2][2], pool[2][2][2], codes[2][2], tcnt[2][2], rq[2], dep_e[2], dep_i[2], rho, phi, E[2], cum[2], th_cp,
-      th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, fedf[2], sort_cnt, sort_seg, total;
+      th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, fedf[2], sort_cnt, sort_seg, cand, dq, total;
   int64_t max_tiles[2];
   int sort_blocks;
 };
@@ -125,6 +125,9 @@ Layout make_layout(const pic_params* p, const pic_xsec* xs) {
   L.sort_blocks = sb;
   L.sort_cnt = take((size_t)sb * (size_t)(nx - 1) * sizeof(uint32_t));
   L.sort_seg = take(256 * sizeof(uint32_t));
+  // candidacy bits of the electron slots of a pipelined step
+  L.cand = take((size_t)((p->capacity[0] + 31) / 32 + 1) * sizeof(uint32_t));
+  L.dq = take((size_t)p->capacity[0] * sizeof(uint32_t));
   L.total = off;
   return L;
 }
@@ -245,6 +248,8 @@ PartArgs particle_args(pic_handle* h, int sp, int parity) {
   // decision codes of alternate passes in alternate buffers: a pass fused
   // with the next step's decisions reads one and writes the other
   a.codes = h->codes[sp][h->csel[sp]];
+  a.cand = sp == 0 ? h->cand : nullptr;
+  a.dq = sp == 0 ? h->dq : nullptr;
   a.acc_ew = h->acc_ew;
   a.eepf = h->eepf;
   a.fedf = h->fedf[sp];
@@ -373,14 +378,14 @@ constexpr int kTailRareBlocks = 128;
 //   another step follows, or the last pass's rare kernel alone;
 //   then a sort or repack of each species when due.
 //
-// Electron steps are pipelined where the schedule allows: the emit of step n
-// then also decides step n+1 (k_emit_decide, k_tail2), so step n+1 has no
-// decide pass. That needs the field of step n+1 before the emit of step n,
-// so it applies to steps that are not the last of a call, not ion steps
-// (the ions' deposit enters that field), not followed by a sort or repack
-// (slots move) and not measuring:
-//   [field(n)] [e_decide(n), storing the pushed state] field(n+1)
-//   e_emit_decide(n) e_tail2(n)
+// Electron steps are pipelined when enabled and the schedule allows: the
+// emit of step n then also decides step n+1 (k_emit_decide, which also runs
+// step n's queued slots), so step n+1 has no decide pass and step n no tail.
+// That needs the field of step n+1 before the emit of step n, so it applies
+// to steps that are not the last of a call, not ion steps (the ions' deposit
+// enters that field), not followed by a sort or repack (slots move) and not
+// measuring:
+//   [field(n)] [e_decide(n)] field_cand(n+1) e_emit_decide(n)
 // A step whose electrons were decided that way (e_pushed) runs e_emit and
 // the electron queued slots on the pushed state.
 struct StepPlan {
@@ -446,6 +451,19 @@ StepPlan plan_step(pic_handle* h, bool field_ready, bool last, bool allow_fuse) 
     // the next step's electron arguments, as its own plan will make them
     q.ae_next = particle_args(h, 0, (int)(h->step & 1));
     h->e_decided = 1;
+    // with the next step's field, the candidacy bits of its electron slots
+    // (their count is the sum of this step's output totals)
+    FieldArgs& f = q.fn;
+    f.cand = h->cand;
+    f.cand_tcnt = q.ae.tcnt;
+    f.cand_count = &h->ctl->n_e[par];
+    f.cand_zero = q.ae_next.tcnt;
+    f.cand_zero_n = h->max_tiles[0];
+    f.cand_cap = h->p.capacity[0];
+    f.cand_thr = q.ae_next.no_coll ? 0ull : q.ae_next.pcoll_thr;
+    f.cand_step = q.ae_next.step;
+    f.seed = h->p.seed;
+    f.run = h->p.run;
   }
   for (int sp = 0; sp < 2 && q.post; ++sp) {
     q.sa[sp] = sort_args(h, sp, q.post == 1);
@@ -479,19 +497,16 @@ int launch_step(pic_handle* h, const StepPlan& q) {
   const int e_pass = timer_begin(h);
   if (!q.e_pushed) {
     const int ev = h->timing >= 2 ? timer_begin(h) : -1;
-    HIP_TRY(launch_particle_kernel(0, 0, q.measure, q.ae, h->launch[0], s, q.fuse ? kLaunchStore : 0));
+    HIP_TRY(launch_particle_kernel(0, 0, q.measure, q.ae, h->launch[0], s));
     timer_end(h, PIC_TIMER_E_DECIDE, ev);
   }
   if (q.fuse) {
     int ev = h->timing >= 2 ? timer_begin(h) : -1;
-    HIP_TRY(launch_field(q.fn, s));
+    HIP_TRY(launch_field_cand(q.fn, h->num_cu, s));
     timer_end(h, PIC_TIMER_FIELD, ev);
     ev = h->timing >= 2 ? timer_begin(h) : -1;
-    HIP_TRY(launch_emit_decide(q.ae, q.ae_next, h->launch[0], s));
+    HIP_TRY(launch_emit_decide(q.ae, q.ae_next, h->launch[0], s, q.e_pushed));
     timer_end(h, PIC_TIMER_E_EMIT, ev);
-    ev = h->timing >= 2 ? timer_begin(h) : -1;
-    HIP_TRY(launch_tail2(q.ae, q.ae_next, h->launch[0], s));
-    timer_end(h, PIC_TIMER_E_RARE, ev);
     timer_end(h, PIC_TIMER_ELECTRON, e_pass);
     return launch_post(h, q, s);
   }
@@ -764,13 +779,15 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
   h->fedf_emax[1] = fedf_ion_emax(p->rf_voltage_v);
   h->sort_cnt = reinterpret_cast<uint32_t*>(w + L.sort_cnt);
   h->sort_seg = reinterpret_cast<uint32_t*>(w + L.sort_seg);
+  h->cand = reinterpret_cast<uint32_t*>(w + L.cand);
+  h->dq = reinterpret_cast<uint32_t*>(w + L.dq);
   h->sort_blocks = L.sort_blocks;
   h->step = 0;
   h->cur[0] = h->cur[1] = 0;
   h->pcur[0] = h->pcur[1] = 0;
   h->cur_hi = 0;
   h->e_decided = 0;
-  h->pipeline = 0;
+  h->pipeline = 1;
   h->measuring = 0;
 
   int st = PIC_OK;

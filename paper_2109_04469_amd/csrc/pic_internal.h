@@ -43,6 +43,18 @@ struct FieldArgs {
   int mode;
   int measuring;
   int parity;
+  // pipelined steps: candidacy bits of the next step's electron slots,
+  // drawn by the other workgroups of k_field_cand (null otherwise)
+  uint32_t* cand;
+  const uint64_t* cand_tcnt;  // the deciding pass's tile totals (their outputs are the slots)
+  const int64_t* cand_count;  // the deciding pass's slot count
+  uint64_t* cand_zero;        // the tile totals the fused pass adds into, zeroed here
+  int64_t cand_zero_n;
+  int64_t cand_cap;
+  uint64_t cand_thr;
+  uint32_t cand_step;
+  uint32_t seed;
+  uint32_t run;
 };
 
 // Particle state of a species: x, v_x and a 4-byte pool index per slot in
@@ -73,6 +85,8 @@ struct PartArgs {
   uint64_t* tcnt_next;  // the other totals buffer: zeroed here for the next pass
   uint4* rq;        // queued slots: (slot, code, output slot, birth rank)
   uint8_t* codes;
+  const uint32_t* cand;          // candidacy bit per slot (electrons, pipelined steps)
+  uint32_t* dq;                  // output slots whose next-step decision is deferred
   double* acc_ew;                // CIC-weighted energy (electrons, measuring)
   unsigned long long* eepf;     // EEPF histogram (electrons, measuring)
   unsigned long long* fedf;     // this species' arrivals per energy bin, [wall][nbins]
@@ -142,6 +156,9 @@ struct SortArgs {
 
 // host launchers
 hipError_t launch_field(const FieldArgs& a, hipStream_t s);
+// the field (workgroup 0) and the candidacy bits a.cand of the next step's
+// electron slots (the other workgroups)
+hipError_t launch_field_cand(const FieldArgs& a, int num_cu, hipStream_t s);
 // grid and LDS bytes of one species' two particle kernels
 struct PartLaunch {
   int grid_decide[2];  // [measuring]
@@ -150,6 +167,8 @@ struct PartLaunch {
   size_t lds_emit;
   int grid_emit_decide;  // the electron emit fused with the next step's decisions
   size_t lds_emit_decide;
+  int grid_emit_decide3;  // the same on input that still needs its push
+  int bpc_emit_decide3;
   int grid_rare;
   int bpc_decide[2];   // resident workgroups per CU at these LDS sizes (occupancy)
   int bpc_emit;
@@ -173,12 +192,13 @@ hipError_t launch_particle_kernel(int kernel, int species, bool measure, const P
 // pushed: electron slots whose input holds the pushed state
 hipError_t launch_tail(int species, const FieldArgs& f, const PartArgs& a, int rare_blocks,
                        hipStream_t s, bool pushed = false);
-// Electron pass a (pushed, decided input) fused with the decisions of the
-// next step b: the emit kernel, then the queued slots of a with their
-// outputs decided for b (and a's tile totals zeroed).
+// Electron pass a fused with the decisions of the next step b: the emit,
+// the queued slots of a with their outputs decided for b, and the outputs
+// whose decisions the streaming part deferred. pushed: a's input holds the
+// pushed state (the previous pipelined step left it); otherwise it is pushed
+// again here.
 hipError_t launch_emit_decide(const PartArgs& a, const PartArgs& b, const PartLaunch& c,
-                              hipStream_t s);
-hipError_t launch_tail2(const PartArgs& a, const PartArgs& b, const PartLaunch& c, hipStream_t s);
+                              hipStream_t s, bool pushed);
 // Batched launches over n discharges (n <= kMaxBatch): args and f are
 // arrays of argument blocks in device memory, one per discharge.
 constexpr int kMaxBatch = 256;
@@ -288,6 +308,8 @@ struct pic_handle {
   double fedf_emax[2];          // upper edge of the arrival energy bins, eV
   uint32_t* sort_cnt;
   uint32_t* sort_seg;
+  uint32_t* cand;  // candidacy bits of a pipelined step's electron slots
+  uint32_t* dq;    // slots of a pipelined step whose decisions are deferred
   int sort_blocks;
   // host-side schedule state
   int64_t step;

@@ -1,5 +1,5 @@
 """Pipelined electron steps against unpipelined ones. With the pipeline on
-(pic_set_pipeline), within one call of pic_step the electron emit of a step
+(pic_set_pipeline; the default), within one call of pic_step the electron emit of a step
 also decides the next step (its push,
 candidacy, wall and collision decisions, deposit and tile totals), so the
 next step has no decide pass; a call of one step never does this. The
@@ -76,13 +76,17 @@ def test_pipelined_steps_equal_single_steps(name):
     init = {0: near_wall_state(w["n_init"][0], L, ve, ve * dt, 3, 0),
             1: near_wall_state(w["n_init"][1], L, vi, vi * dt * p["ion_subcycle"], 3, 1)}
     many, single = _pair(p, xs, init)
+    off = _pair(p, xs, init)[0]
     many.set_pipeline(True)
+    off.set_pipeline(False)
     for k, n in enumerate((1, 2, 37, 9, 300)):
         print(f"[pipeline] {name}: call {k} of {n} steps", flush=True)
         many.step(n)
+        off.step(n)
         for _ in range(n):
             single.step(1)
         _same(many, single, f"{name} after call {k}")
+        _same(off, single, f"{name} unpipelined, after call {k}")
 
 
 def test_pipelined_steps_with_measurement_switching():
