@@ -285,7 +285,7 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
 // collect in LDS until one flush at the end. sH (and, measuring, sEW) are all
 // zero on entry and on exit; sE holds a's field; s_lo > s_hi on entry and on
 // exit, and the caller synchronises the workgroup before the next call.
-template <int SP, bool MEASURE, bool STORE = false>
+template <int SP, bool MEASURE>
 __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int t_end, int t_step,
                                              int64_t n_push, int64_t n_tot, const double* sE,
                                              unsigned long long* sH, double* sEW,
@@ -372,26 +372,6 @@ __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int
       for (int q = 0; q < 4; ++q)
         if (need[q])
           decide_rare<SP, MEASURE>(a, s_cnt, s0 + q, cand[q], xs[q], vxs[q], c[q], o[q], b[q]);
-      if (STORE) {
-        // the pushed state (mirrored where reflected) replaces the slot's
-        // input, so the emit and the queued-slot work of this pass need not
-        // push again; every slot of the run was read above by this thread
-        double* xw = const_cast<double*>(a.xin);
-        double* vw = const_cast<double*>(a.vxin);
-        if (full && s0 + 3 < n_push) {
-          reinterpret_cast<double2*>(xw + s0)[0] = make_double2(xs[0], xs[1]);
-          reinterpret_cast<double2*>(xw + s0)[1] = make_double2(xs[2], xs[3]);
-          reinterpret_cast<double2*>(vw + s0)[0] = make_double2(vxs[0], vxs[1]);
-          reinterpret_cast<double2*>(vw + s0)[1] = make_double2(vxs[2], vxs[3]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (s0 + q < n_push) {
-              xw[s0 + q] = xs[q];
-              vw[s0 + q] = vxs[q];
-            }
-        }
-      }
 
       // deposit of the new positions (an ionization electron is born at its
       // parent's position), combined when the four share a cell
@@ -492,7 +472,7 @@ __device__ __forceinline__ void clear_next_totals(const PartArgs& a) {
     a.tcnt_next[i] = 0ull;
 }
 
-template <int SP, bool MEASURE, bool STORE>
+template <int SP, bool MEASURE>
 __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nx = a.nx;
@@ -540,7 +520,7 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
   }
   __syncthreads();
 
-  decide_tiles<SP, MEASURE, STORE>(a, blockIdx.x, ntiles, gridDim.x, n_push, n_tot, sE, sH, sEW,
+  decide_tiles<SP, MEASURE>(a, blockIdx.x, ntiles, gridDim.x, n_push, n_tot, sE, sH, sEW,
                                    sEEPF, s_lo, s_hi, s_cnt);
 
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
@@ -587,32 +567,6 @@ __device__ __forceinline__ void reload(const PartArgs& a, const double* E, int64
   repush(a, E, c, x, vx);
 }
 
-// Electron decision of step b.step for the single slot `slot` of that
-// step's arrays, holding x, vx (the state the previous step left) and pool
-// entry id: field at the particle from E (b's field, in LDS or global
-// memory), the push, and for the few slots that left the gap or are
-// candidates (cand: the slot's candidacy bit, Philox word slot mod 4 of
-// the block (step, slot / 4, 4, 0) below the threshold, drawn with the
-// step's field) the wall and collision decisions. The same arithmetic as
-// decide_tiles, one slot at a time. x and vx become the pushed state
-// (mirrored when reflected); c, o, bb: decision code, own outputs and
-// births of the slot in step b.step.
-__device__ __forceinline__ void decide_one(const PartArgs& b, const double* E, int64_t slot,
-                                           double& x, double& vx, uint32_t id,
-                                           unsigned long long* s_cnt, bool cand, uint32_t& c,
-                                           uint32_t& o, uint32_t& bb) {
-  int j;
-  double f;
-  int64_t w1;
-  cell_of(x, b.inv_dx, b.nx, j, f, w1);
-  push(E, j, f, b.acc, b.dts, x, vx);
-  c = kCodePushed;
-  o = 1u;
-  bb = 0u;
-  if (cand || !(x >= 0.0 && x <= b.L) || !isfinite(vx))
-    decide_rare<0, false>(b, s_cnt, slot, cand, x, vx, c, o, bb, id);
-}
-
 // Tile totals word of one slot's outcome: outputs | births << 16 |
 // queued << 32.
 __device__ __forceinline__ unsigned long long totals_word(uint32_t c, uint32_t o, uint32_t bb) {
@@ -657,15 +611,19 @@ __device__ __forceinline__ void emit_empty(DevCtl* ctl, int par) {
 // slot order from the same scans.
 //
 // MODE 0: the input holds the state before the push, which is repeated
-// here (sE: a's field). MODE 1: the input holds the pushed state (k_decide
-// stored it), written out as it is. MODE 2 (electrons): as MODE 1, and each
-// output that needs no queued work is then decided for the next step b
-// (decide_one with b's field in sE): the output slot receives the pushed
-// state of that step, its decision code goes to b.codes, its deposit to the
-// LDS histogram sH (flushed by the caller over [jlo, jhi]), its outcome to
-// the next pass's tile totals b.tcnt, its events to s_cnt. MODE 3: as MODE 2
-// on an input that holds the state before the push, which is repeated first
-// with a's field (in sE0).
+// here (sE: a's field). MODE 1: the input holds the pushed state (the
+// previous step's fused emit stored it), written out as it is. MODE 2
+// (electrons): as MODE 1, and each output that needs no queued work is then
+// pushed for the next step b with b's field in sE; an output that stays in
+// the gap and is no collision candidate (its bit in b.cand) is decided there:
+// the output slot receives the pushed state of that step, its decision code
+// goes to b.codes, its deposit to the LDS histogram sH (flushed by the caller
+// over [jlo, jhi]), its outcome to the next pass's tile totals b.tcnt. The
+// other outputs are listed in b.dq from this workgroup's first output slot
+// on (their count in s_dcnt), and rq_range returns the workgroup's queued
+// slots [rq_range[0], rq_range[1]) and first output slot rq_range[2], for
+// the caller to finish. MODE 3: as MODE 2 on an input that holds the state
+// before the push, which is repeated first with a's field (in sE0).
 template <int SP, int STAGE_PER, int MODE = 0>
 __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, int t_step,
                                            int ntiles, int64_t n_tot, int64_t bbase, double* sE,
@@ -1108,11 +1066,11 @@ __device__ __forceinline__ void deposit_global_n(unsigned long long* dep, double
   atomicAdd(&dep[j + 1], (unsigned long long)mul * (unsigned long long)w1);
 }
 
-// An electron output of pass a at slot dest (state x, vx after a's step,
-// pool entry id already written) decided for the next step b, one slot at a
-// time: decide_one with b's field from global memory, the decision code,
-// the next pass's tile totals and the deposit with global atomics, and the
-// pushed state stored at the slot.
+// An electron output of pass a at slot dest (state x, vx, vy, vz after a's
+// step, pool entry id already written) decided for the next step b, one slot
+// at a time: the push with b's field, the wall and collision decisions where
+// needed, the decision code, the next pass's tile totals and the deposit with
+// global atomics, and the pushed state stored at the slot.
 // ef[2]: b's field at the two nodes of x's cell and cw the candidacy word of
 // dest, loaded by the caller ahead of the collision kinematics.
 __device__ __forceinline__ void next_step_output(const PartArgs& a, const PartArgs& b,
@@ -1141,8 +1099,8 @@ __device__ __forceinline__ void next_step_output(const PartArgs& a, const PartAr
 
 // VAR: the method-variant paths (anisotropic elastic scattering, Opal
 // sharing) are compiled in; without them the kernels stay smaller.
-// PUSHED: the slot's input holds the pushed state (k_decide stored it), so
-// it is not pushed again. FUSED (electrons, with PUSHED): the outputs are
+// PUSHED: the slot's input holds the pushed state (the previous step's
+// fused emit stored it), so it is not pushed again. FUSED (electrons, with PUSHED): the outputs are
 // then decided for the next step nb (next_step_output).
 template <int SP, bool VAR, bool PUSHED = false, bool FUSED = false>
 __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long* s_cnt,
@@ -1758,10 +1716,10 @@ PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, in
     c.lds_decide[m] = decide_lds(nx, m == 1, nbins);
     int bpc;
     if (species == 0)
-      bpc = m ? blocks_per_cu(k_decide<0, true, false>, c.lds_decide[m], kDB)
-              : blocks_per_cu(k_decide<0, false, false>, c.lds_decide[m], kDB);
+      bpc = m ? blocks_per_cu(k_decide<0, true>, c.lds_decide[m], kDB)
+              : blocks_per_cu(k_decide<0, false>, c.lds_decide[m], kDB);
     else
-      bpc = blocks_per_cu(k_decide<1, false, false>, c.lds_decide[m], kDB);
+      bpc = blocks_per_cu(k_decide<1, false>, c.lds_decide[m], kDB);
     c.grid_decide[m] = clamp_grid((int64_t)bpc * num_cu, max_tiles);
     c.bpc_decide[m] = bpc;
   }
@@ -1797,22 +1755,17 @@ void particle_launch_set(PartLaunch& c, int num_cu, int kd, int ke) {
 hipError_t launch_particle_kernel(int kernel, int species, bool measure, const PartArgs& a,
                                   const PartLaunch& c, hipStream_t s, int flags) {
   const int m = (species == 0 && measure) ? 1 : 0;
-  const bool store = (flags & kLaunchStore) != 0;
   const bool pushed = (flags & kLaunchPushed) != 0;
-  if (species == 1 && (store || pushed)) return hipErrorInvalidValue;
+  if (species == 1 && pushed) return hipErrorInvalidValue;
   if (kernel == 0) {
     const dim3 g(c.grid_decide[m]), t(kDB);
     const size_t lds = c.lds_decide[m];
     if (species == 1)
-      hipLaunchKernelGGL((k_decide<1, false, false>), g, t, lds, s, a);
-    else if (m && store)
-      hipLaunchKernelGGL((k_decide<0, true, true>), g, t, lds, s, a);
+      hipLaunchKernelGGL((k_decide<1, false>), g, t, lds, s, a);
     else if (m)
-      hipLaunchKernelGGL((k_decide<0, true, false>), g, t, lds, s, a);
-    else if (store)
-      hipLaunchKernelGGL((k_decide<0, false, true>), g, t, lds, s, a);
+      hipLaunchKernelGGL((k_decide<0, true>), g, t, lds, s, a);
     else
-      hipLaunchKernelGGL((k_decide<0, false, false>), g, t, lds, s, a);
+      hipLaunchKernelGGL((k_decide<0, false>), g, t, lds, s, a);
   } else if (kernel == 1) {
     const dim3 g(c.grid_emit), t(kBlock);
     if (species == 1)

@@ -180,10 +180,9 @@ PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, in
 // to [1, occupancy] and to the tile count)
 void particle_launch_set(PartLaunch& c, int num_cu, int kd, int ke);
 // kernel 0: k_decide, 1: k_emit, 2: k_rare (launched in this order).
-// flags (electrons only): kLaunchStore, the decide kernel stores the pushed
-// state in place of its input; kLaunchPushed, the emit and rare kernels take
-// that pushed input (no second push).
-constexpr int kLaunchStore = 1;
+// flags (electrons only): kLaunchPushed, the emit and rare kernels take an
+// input that holds the pushed state (the previous step's fused emit decided
+// this step and stored it), with no second push.
 constexpr int kLaunchPushed = 2;
 hipError_t launch_particle_kernel(int kernel, int species, bool measure, const PartArgs& a,
                                   const PartLaunch& c, hipStream_t s, int flags = 0);
