@@ -713,26 +713,64 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         }
       }
     }
+    // the fused pass: the next step's candidacy bits of this tile's outputs
+    // (at most 2 kTile slots from the tile's first output), one word per
+    // thread, requested with the tile's loads and put into LDS before the
+    // tile's barrier
+    static_assert(kCandWords <= kBlock, "one candidacy word per thread");
+    uint32_t cw_tile = 0u;
     if (FUSE) {
-      // the next step's candidacy bits of this tile's outputs (at most
-      // 2 kTile slots from the tile's first output), into LDS with the loads
-      // of the tile
       const int64_t w0 = prefO >> 5;
       const int64_t nwords = (a.cap + 31) / 32 + 1;
-      for (int i = tid; i < kCandWords; i += kBlock)
-        s_cand[p][i] = w0 + i < nwords ? b->cand[w0 + i] : 0u;
+      if (tid < kCandWords && w0 + tid < nwords) cw_tile = b->cand[w0 + tid];
     }
     // pairs of consecutive slots per lane: 16-byte loads of x and v_x, an
-    // 8-byte load of the two pool indices, one 2-byte load of the codes;
-    // each pair row's count and wave scan follow its loads (issuing every
-    // row's loads first measured slower)
+    // 8-byte load of the two pool indices, one 2-byte load of the codes.
+    // The plain emit counts and scans each pair row after its own loads
+    // (issuing every row's loads first measured slower there); the fused
+    // pass, latency-bound at three workgroups per CU, requests the codes of
+    // all rows of a whole tile first and then every row's x, v_x and
+    // indices, so the tile waits for one round trip before its counts
+    // instead of one per row.
     uint32_t code[kPPT], loc[kEPairs], rloc[kEPairs];
     double px[kPPT], pvx[kPPT];
     uint32_t pid[kPPT];
+    // a whole tile (all but the last of a pass): no slot tests, so that the
+    // loads are issued back to back
+    const bool whole = FUSE && base + kTile <= n_tot;
+    if (whole) {
+#pragma unroll
+      for (int k = 0; k < kEPairs; ++k) {
+        const int64_t s0 = base + k * (2 * kBlock) + 2 * tid;
+        // the two slots' codes (bytes 0, 1) and presence flags (bits 16, 17)
+        code[2 * k] = (uint32_t)*reinterpret_cast<const uint16_t*>(a.codes + s0) | 0x30000u;
+      }
+#pragma unroll
+      for (int k = 0; k < kEPairs; ++k) {
+        const int64_t s0 = base + k * (2 * kBlock) + 2 * tid;
+        const double2 xx = *reinterpret_cast<const double2*>(a.xin + s0);
+        const double2 vv = *reinterpret_cast<const double2*>(a.vxin + s0);
+        const uint2 ii = *reinterpret_cast<const uint2*>(a.idin + s0);
+        px[2 * k] = xx.x;
+        px[2 * k + 1] = xx.y;
+        pvx[2 * k] = vv.x;
+        pvx[2 * k + 1] = vv.y;
+        pid[2 * k] = ii.x;
+        pid[2 * k + 1] = ii.y;
+      }
+#pragma unroll
+      for (int k = 0; k < kEPairs; ++k) {
+        // each slot's code with its presence flag in bit 8
+        const uint32_t c2 = code[2 * k];
+        code[2 * k] = (c2 & 0xFFu) | ((c2 >> 8) & 0x100u);
+        code[2 * k + 1] = ((c2 >> 8) & 0xFFu) | ((c2 >> 9) & 0x100u);
+      }
+    }
 #pragma unroll
     for (int k = 0; k < kEPairs; ++k) {
       const int64_t s0 = base + k * (2 * kBlock) + 2 * tid;
       uint32_t cnt = 0, rcnt = 0;
+      if (!whole) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         code[2 * k + h] = 0;
@@ -757,6 +795,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         px[2 * k] = a.xin[s0];
         pvx[2 * k] = a.vxin[s0];
         pid[2 * k] = a.idin[s0];
+      }
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -785,6 +824,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         s_ps[p][2][wave] = wr;
       }
     }
+    if (FUSE && tid < kCandWords) s_cand[p][tid] = cw_tile;
     __syncthreads();
     // every wave scans the tile's segment totals (segment k * nw + w) itself,
     // so no second barrier is needed; the other copy of the totals belongs
