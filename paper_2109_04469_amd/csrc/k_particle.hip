@@ -1039,8 +1039,12 @@ __global__ __launch_bounds__(kBlock) void k_emit(PartArgs a) {
   // inside one moving window of the arrays (measured 12 % faster for them).
   int t0, t1, t_step;
   if (SP == 0) {
-    t0 = uniform32((int)((int64_t)ntiles * blockIdx.x / gridDim.x));
-    t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
+    // the longer runs on the workgroups dispatched first on each CU (as in
+    // k_emit_decide)
+    const int g = (int)gridDim.x, b_ = (int)blockIdx.x;
+    const int q = ntiles / g, r = ntiles % g;
+    t0 = b_ < r ? b_ * (q + 1) : r * (q + 1) + (b_ - r) * q;
+    t1 = t0 + (b_ < r ? q + 1 : q);
     t_step = 1;
   } else {
     t0 = blockIdx.x;
@@ -1429,8 +1433,14 @@ __global__ __launch_bounds__(kBlock, EMIT_DECIDE_MIN_WAVES) void k_emit_decide(P
     }
     return;
   }
-  const int t0 = uniform32((int)((int64_t)ntiles * blockIdx.x / gridDim.x));
-  const int t1 = uniform32((int)((int64_t)ntiles * (blockIdx.x + 1) / gridDim.x));
+  // contiguous runs, the longer ones (one tile more) on the lower workgroup
+  // indices: those are dispatched first on each CU, and the oldest waves of
+  // a CU are issued first, so they stream faster (measured: workgroups
+  // dispatched third on their CU took about 40 % longer per tile)
+  const int g = (int)gridDim.x, b_ = (int)blockIdx.x;
+  const int q = ntiles / g, r = ntiles % g;
+  const int t0 = b_ < r ? b_ * (q + 1) : r * (q + 1) + (b_ - r) * q;
+  const int t1 = t0 + (b_ < r ? q + 1 : q);
   __syncthreads();  // sH, s_cnt, s_lo, s_hi set
   if (t0 >= t1) return;
 
