@@ -1098,8 +1098,11 @@ __device__ __forceinline__ void aniso_dir(double ex, double ey, double ez, doubl
   nz = c * ez + sn * (cp * b1z + sp * b2z);
 }
 
-// deposit_global with weight mul (an ionization electron and its parent
-// share a position)
+// The deposit of one position with weight mul (an ionization electron and
+// its parent share a position) into a histogram: global memory, or the
+// fused emit's LDS histogram, which the workgroup flushes once at its end
+// (device-scope atomics of every workgroup on the few lines of the deposit
+// array stalled single items of the fused emit by up to 20 us).
 __device__ __forceinline__ void deposit_global_n(unsigned long long* dep, double x, double inv_dx,
                                                  int nx, uint32_t mul) {
   int j;
@@ -1113,14 +1116,16 @@ __device__ __forceinline__ void deposit_global_n(unsigned long long* dep, double
 // An electron output of pass a at slot dest (state x, vx, vy, vz after a's
 // step, pool entry id already written) decided for the next step b, one slot
 // at a time: the push with b's field, the wall and collision decisions where
-// needed, the decision code, the next pass's tile totals and the deposit with
-// global atomics, and the pushed state stored at the slot.
+// needed, the decision code, the next pass's tile totals and the deposit
+// (into sH, the workgroup's LDS histogram), and the pushed state stored at
+// the slot.
 // ef[2]: b's field at the two nodes of x's cell and cw the candidacy word of
 // dest, loaded by the caller ahead of the collision kinematics.
 __device__ __forceinline__ void next_step_output(const PartArgs& a, const PartArgs& b,
                                                  unsigned long long* s_cnt, int64_t dest,
                                                  double x, double vx, double vy, double vz,
-                                                 uint32_t id, const double* ef, uint32_t cw) {
+                                                 uint32_t id, const double* ef, uint32_t cw,
+                                                 unsigned long long* sH) {
   uint32_t c2 = kCodePushed, o2 = 1u, b2 = 0u;
   int j;
   double f;
@@ -1137,7 +1142,7 @@ __device__ __forceinline__ void next_step_output(const PartArgs& a, const PartAr
   }
   b.codes[dest] = (uint8_t)c2;
   atomicAdd(&b.tcnt[dest / kTile], totals_word(c2, o2, b2));
-  if (o2) deposit_global_n(b.dep_own, x, b.inv_dx, b.nx, o2);
+  if (o2) deposit_global_n(sH, x, b.inv_dx, b.nx, o2);
   store3(a, dest, x, vx, id);
 }
 
@@ -1149,7 +1154,8 @@ __device__ __forceinline__ void next_step_output(const PartArgs& a, const PartAr
 template <int SP, bool VAR, bool PUSHED = false, bool FUSED = false>
 __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long* s_cnt,
                                           int64_t slot, uint32_t c, int64_t dest, int64_t r,
-                                          int64_t bbase, const PartArgs* nb = nullptr) {
+                                          int64_t bbase, const PartArgs* nb = nullptr,
+                                          unsigned long long* sHn = nullptr) {
   static_assert(!FUSED || SP == 0, "only electron slots are fused");
   const uint32_t step = a.step;
   const double L = a.L;
@@ -1298,13 +1304,13 @@ __device__ __forceinline__ void rare_slot(const PartArgs& a, unsigned long long*
       // pool entries first: the next step's decision reads them
       a.pvy[id] = vy;
       a.pvz[id] = vz;
-      if (dest < a.cap) next_step_output(a, *nb, s_cnt, dest, x, vx, vy, vz, id, ef, cw0);
+      if (dest < a.cap) next_step_output(a, *nb, s_cnt, dest, x, vx, vy, vz, id, ef, cw0, sHn);
       if (child) {
         const int64_t cid = a.ctl->pbase[SP] + r;
         if (dest + 1 < a.cap && cid < a.pcap) {
           a.pvy[cid] = cvy;
           a.pvz[cid] = cvz;
-          next_step_output(a, *nb, s_cnt, dest + 1, x, cvx, cvy, cvz, (uint32_t)cid, ef, cw1);
+          next_step_output(a, *nb, s_cnt, dest + 1, x, cvx, cvy, cvz, (uint32_t)cid, ef, cw1, sHn);
         }
       }
     } else {
@@ -1353,18 +1359,14 @@ __global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// The electron emit of pass a fused with the electron decisions of the next
-// step b (emit_tiles MODE 2): a's input holds pushed, decided state; the
-// outputs that need no queued work leave pushed and decided for b, so the
-// next step has no decide pass of its own. Contiguous runs of tiles per
-// workgroup (as k_emit for electrons); b's field in LDS with the deposit
-// histogram, flushed once per workgroup.
 // An output at slot dest that the fused emit pushed for step b but left
 // undecided (it left the gap or is a collision candidate): the wall and
-// collision decisions, the decision code, the tile totals and the deposit,
-// and the (possibly mirrored) pushed state stored back.
+// collision decisions, the decision code, the tile totals, the deposit into
+// the workgroup's LDS histogram sH, and the (possibly mirrored) pushed state
+// stored back.
 __device__ __forceinline__ void deferred_decision(const PartArgs& a, const PartArgs& b,
-                                                  unsigned long long* s_cnt, int64_t dest) {
+                                                  unsigned long long* s_cnt, int64_t dest,
+                                                  unsigned long long* sH) {
   double x = a.xout[dest], vx = a.vxout[dest];
   const uint32_t id = a.idout[dest];
   const bool cand = ((b.cand[dest >> 5] >> (dest & 31)) & 1u) != 0;
@@ -1377,11 +1379,18 @@ __device__ __forceinline__ void deferred_decision(const PartArgs& a, const PartA
   decide_rare<0, false, true>(b, s_cnt, dest, cand, x, vx, c, o, bb, id, vyz);
   b.codes[dest] = (uint8_t)c;
   atomicAdd(&b.tcnt[dest / kTile], totals_word(c, o, bb));
-  if (o) deposit_global_n(b.dep_own, x, b.inv_dx, b.nx, o);
+  if (o) deposit_global_n(sH, x, b.inv_dx, b.nx, o);
   a.xout[dest] = x;
   a.vxout[dest] = vx;
 }
 
+// The electron emit of pass a fused with the electron decisions of the next
+// step b (emit_tiles MODE 2): a's input holds pushed, decided state; the
+// outputs that need no queued work leave pushed and decided for b, so the
+// next step has no decide pass of its own. Contiguous runs of tiles per
+// workgroup (as k_emit for electrons); b's field in LDS with the deposit
+// histogram, which also takes the rare items' deposits and is flushed once
+// per workgroup at its end.
 // MODE 2: a's input holds the pushed, decided state; MODE 3: the state
 // before the push (the first pipelined step after a plain decide), pushed
 // again here with a's field.
@@ -1406,7 +1415,6 @@ __global__ __launch_bounds__(kBlock, EMIT_DECIDE_MIN_WAVES) void k_emit_decide(P
   __shared__ uint32_t s_ps[2][3][kBlock / kWave];
   __shared__ uint64_t s_red[3][kBlock / kWave];
   __shared__ unsigned long long s_cnt[NCOUNTERS];
-  __shared__ int s_lo, s_hi;
   __shared__ uint32_t s_cand[2][kCandWords];
   __shared__ uint32_t s_dcnt[2];
 
@@ -1416,11 +1424,7 @@ __global__ __launch_bounds__(kBlock, EMIT_DECIDE_MIN_WAVES) void k_emit_decide(P
   const int par = a.parity;
   for (int j = tid; j < nx; j += kBlock) sH[j] = 0ull;
   if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
-  if (tid == 0) {
-    s_lo = INT_MAX;
-    s_hi = -1;
-    s_dcnt[0] = s_dcnt[1] = 0u;
-  }
+  if (tid == 0) s_dcnt[0] = s_dcnt[1] = 0u;
 
   int64_t n_tot = uniform64(ctl->n_e[par]);
   if (n_tot > a.cap) n_tot = a.cap;  // the decide has latched the error
@@ -1441,7 +1445,7 @@ __global__ __launch_bounds__(kBlock, EMIT_DECIDE_MIN_WAVES) void k_emit_decide(P
   const int q = ntiles / g, r = ntiles % g;
   const int t0 = b_ < r ? b_ * (q + 1) : r * (q + 1) + (b_ - r) * q;
   const int t1 = t0 + (b_ < r ? q + 1 : q);
-  __syncthreads();  // sH, s_cnt, s_lo, s_hi set
+  __syncthreads();  // sH, s_cnt, s_dcnt set
   if (t0 >= t1) return;
 
   int jlo = INT_MAX, jhi = -1;
@@ -1449,20 +1453,8 @@ __global__ __launch_bounds__(kBlock, EMIT_DECIDE_MIN_WAVES) void k_emit_decide(P
   emit_tiles<0, (kMaxNx + kBlock - 1) / kBlock, MODE>(a, t0, t1, 1, ntiles, n_tot, bbase, sE,
                                                       s_wtot, s_wr, s_ps, s_red, &b, sH, s_cnt,
                                                       &jlo, &jhi, s_cand, s_dcnt, sE0, rq_range);
-  // one flush of the deposit range of this workgroup's outputs
-  jlo = wave_min(jlo);
-  jhi = wave_max(jhi);
-  if (lane == 0) {
-    atomicMin(&s_lo, jlo);
-    atomicMax(&s_hi, jhi);
-  }
-  __syncthreads();
-  const int lo = s_lo, hi = s_hi;
-  for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += kBlock) {
-    const unsigned long long v = sH[j];
-    if (v) atomicAdd(&b.dep_own[j], v);
-  }
-  // this workgroup's queued slots and deferred decisions
+  // this workgroup's queued slots and deferred decisions, their deposits
+  // into the same LDS histogram
   const int64_t q0 = uniform64(rq_range[0]);
   const int64_t nq = uniform64(rq_range[1]) - q0;
   const int64_t out0 = uniform64(rq_range[2]);
@@ -1472,11 +1464,17 @@ __global__ __launch_bounds__(kBlock, EMIT_DECIDE_MIN_WAVES) void k_emit_decide(P
   for (int64_t i = tid; i < nq; i += kBlock) {
     const uint4 q = a.rq[q0 + i];
     rare_slot<0, VAR, MODE == 2, true>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w,
-                                       bbase, &b);
+                                       bbase, &b, sH);
   }
   for (int64_t i = kBlock - 1 - tid; i < nd; i += kBlock)
-    deferred_decision(a, b, s_cnt, (int64_t)a.dq[out0 + i]);
+    deferred_decision(a, b, s_cnt, (int64_t)a.dq[out0 + i], sH);
   __syncthreads();
+  // one flush of the histogram over the cells the workgroup's outputs and
+  // rare items touched
+  for (int j = tid; j < nx; j += kBlock) {
+    const unsigned long long v = sH[j];
+    if (v) atomicAdd(&b.dep_own[j], v);
+  }
   if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
 }
 
