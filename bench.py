@@ -299,6 +299,8 @@ def main():
                          "1000 RF cycles, training on 40, 6 warm runs of 1000 cycles), full (about 10 "
                          "GPU-minutes: 112 cold runs of 2000 cycles, 16 warm runs of 2000) or none")
     ap.add_argument("--no-c1", action="store_true", help="skip the small discharge in full")
+    ap.add_argument("--tune-steps", type=int, default=40,
+                    help="steps per candidate of the particle-pass tuner (with the sweep)")
     ap.add_argument("--pipeline", choices=("on", "off"), default="on",
                     help="pipelined electron steps (pic_set_pipeline) for the timed workload")
     args = ap.parse_args()
@@ -454,9 +456,21 @@ def main():
     }
     out["sweep"] = None
     if not args.no_sweep:
+        # the per-discharge tuner on the timed workload (after the timed
+        # windows): every candidate schedule and launch shape of the particle
+        # passes, timed on the discharge itself, and the one it keeps
+        log("[bench] tuner: particle-pass candidates on the timed workload")
+        tuned = d.tune_pass(steps_per_trial=args.tune_steps)
         del d
         torch.cuda.empty_cache()
         out["sweep"] = sweep_measurement(torch, args.sweep_steps, log=log)
+        out["sweep"]["tuner"] = {
+            "workload": w["name"], "steps_per_trial": args.tune_steps,
+            "unit": "us of particle passes (electron + ion) per step, events around the passes",
+            "trials": tuned["trials"], "choice": tuned["trials"][tuned["best"]],
+            "note": "pipelined: fused emit-and-decide kernel at 1..3 workgroups per CU; unpipelined: "
+                    "separate decide and emit kernels at each decide shape, then each emit shape",
+        }
     out["warm_start"] = None
     if args.warm_start != "none":
         from paper_2109_04469_amd import warmstart

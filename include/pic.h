@@ -365,7 +365,35 @@ int pic_set_pipeline(pic_handle* h, int on);
  * NULL). The steps are ordinary steps of the discharge. Synchronises. */
 int pic_tune(pic_handle* h, int64_t steps_per_trial, int* decide_wg_per_cu, int* emit_wg_per_cu);
 
-/* Kernel timing with HIP events recorded on the handle's stream
+/* One candidate configuration of the particle passes that pic_tune_pass
+ * timed: the electron schedule (pic_set_pipeline), the launch shape
+ * (pic_set_launch) and the measured time of the particle passes (electron
+ * and ion passes with their kernels back to back, PIC_TIMER_ELECTRON +
+ * PIC_TIMER_ION) per step, microseconds. */
+typedef struct {
+  int pipeline;
+  int decide_wg_per_cu;
+  int emit_wg_per_cu;
+  double us_per_step;
+} pic_pass_trial;
+
+/* Chooses the particle passes' compiled kernels and launch shape by
+ * measurement on the discharge itself: pipelined electron steps (the fused
+ * emit-and-decide kernel) at each of its workgroups per CU, then unpipelined
+ * steps (separate decide and emit kernels) at each decide shape and each
+ * emit shape at the best decide shape. Each candidate advances the
+ * discharge by steps_per_trial ordinary steps with events around the
+ * passes; the fastest is kept (pic_set_pipeline, pic_set_launch). trials: a
+ * caller-owned host array of max_trials entries (NULL with max_trials 0)
+ * that receives the candidates in the order timed; n_trials: their count;
+ * best: the index of the chosen one (both may be NULL). Results do not
+ * depend on the choice: every candidate computes the same steps bit for bit
+ * (Sec. 2 defines one step; the candidates regroup its work). Synchronises;
+ * on an error the schedule is left as it was. */
+int pic_tune_pass(pic_handle* h, int64_t steps_per_trial, pic_pass_trial* trials, int max_trials,
+                  int* n_trials, int* best);
+
+/* Kernel timing with HIP events recorded on the handle's stream/* Kernel timing with HIP events recorded on the handle's stream
  * (measurement surface). level 0: off. level 1: two event records around
  * the field kernel, each species' particle pass (PIC_TIMER_ELECTRON,
  * PIC_TIMER_ION: its decide, emit and rare kernels back to back, the gaps

@@ -1389,6 +1389,84 @@ int pic_tune(pic_handle* h, int64_t steps_per_trial, int* decide_wg_per_cu, int*
   return latched(h);
 }
 
+int pic_tune_pass(pic_handle* h, int64_t steps_per_trial, pic_pass_trial* trials, int max_trials,
+                  int* n_trials, int* best) {
+  if (!h || steps_per_trial < 1 || max_trials < 0 || (max_trials > 0 && !trials)) return PIC_EINVAL;
+  // the particle passes' time per step over steps_per_trial ordinary steps,
+  // with events around each pass (timing level 1), without disturbing the
+  // caller's accumulated timers
+  const int level = h->timing;
+  const int pipeline0 = h->pipeline;
+  auto trial = [&](double* us) -> int {
+    int st = timer_collect(h);
+    if (st) return st;
+    double ms0[2];
+    int64_t n0[2];
+    const int tm[2] = {PIC_TIMER_ELECTRON, PIC_TIMER_ION};
+    for (int k = 0; k < 2; ++k) {
+      ms0[k] = h->t_ms[tm[k]];
+      n0[k] = h->t_n[tm[k]];
+    }
+    h->timing = 1;
+    st = pic_step(h, steps_per_trial);
+    if (!st) st = timer_collect(h);
+    h->timing = level;
+    if (st) return st;
+    double ms = 0.0;
+    for (int k = 0; k < 2; ++k) {
+      ms += h->t_ms[tm[k]] - ms0[k];
+      h->t_ms[tm[k]] = ms0[k];
+      h->t_n[tm[k]] = n0[k];
+    }
+    *us = 1e3 * ms / (double)steps_per_trial;
+    return PIC_OK;
+  };
+  const PartLaunch& c = h->launch[0];
+  int n = 0, ib = -1;
+  pic_pass_trial bestt{};
+  auto run = [&](int pipe, int kd, int ke, double* us) -> int {
+    h->pipeline = pipe;
+    pic_set_launch(h, kd, ke);
+    pic_pass_trial t{pipe, kd, ke, 0.0};
+    const int st = trial(&t.us_per_step);
+    if (st) return st;
+    if (n < max_trials) trials[n] = t;
+    if (ib < 0 || t.us_per_step < bestt.us_per_step) {
+      ib = n;
+      bestt = t;
+    }
+    ++n;
+    *us = t.us_per_step;
+    return PIC_OK;
+  };
+  int st = PIC_OK;
+  double us = 0.0;
+  // pipelined: the fused emit's workgroups per CU (its decide pass runs only
+  // on the steps that cannot be pipelined, at the most that fit)
+  const int kd_max = c.bpc_decide[0];
+  for (int k = 1; k <= c.bpc_emit_decide && !st; ++k) st = run(1, kd_max, k, &us);
+  // unpipelined: each decide shape, then each emit shape at the best decide
+  int kd_best = kd_max;
+  double kd_us = -1.0;
+  for (int k = 1; k <= kd_max && !st; ++k) {
+    st = run(0, k, c.bpc_emit, &us);
+    if (!st && (kd_us < 0.0 || us < kd_us)) {
+      kd_us = us;
+      kd_best = k;
+    }
+  }
+  for (int k = 1; k < c.bpc_emit && !st; ++k) st = run(0, kd_best, k, &us);
+  if (st) {
+    h->pipeline = pipeline0;
+    return st;
+  }
+  h->pipeline = bestt.pipeline;
+  pic_set_launch(h, bestt.decide_wg_per_cu, bestt.emit_wg_per_cu);
+  if (n_trials) *n_trials = n;
+  if (best) *best = ib;
+  return latched(h);
+}
+
 int pic_timing(pic_handle* h, int level) {
   if (!h || level < 0 || level > 2) return PIC_EINVAL;
   h->timing = level;

@@ -228,6 +228,23 @@ class Discharge:
               "pic_tune")
         return kd.value, ke.value
 
+    def tune_pass(self, steps_per_trial=40):
+        """Times the particle passes' candidate schedules and launch shapes on
+        this discharge (advancing it by steps_per_trial steps per candidate)
+        and keeps the fastest; returns {"trials": [...], "best": index}, each
+        trial a dict of pipeline, decide_wg_per_cu, emit_wg_per_cu and
+        us_per_step."""
+        from .capi import PicPassTrial
+
+        arr = (PicPassTrial * 32)()
+        n, best = ctypes.c_int(), ctypes.c_int()
+        check(self.L.pic_tune_pass(self.h, int(steps_per_trial), arr, 32, ctypes.byref(n),
+                                   ctypes.byref(best)), "pic_tune_pass")
+        trials = [{"pipeline": bool(t.pipeline), "decide_wg_per_cu": t.decide_wg_per_cu,
+                   "emit_wg_per_cu": t.emit_wg_per_cu, "us_per_step": t.us_per_step}
+                  for t in arr[:min(n.value, 32)]]
+        return {"trials": trials, "best": best.value}
+
     def timing(self, level=1):
         """0: off; 1: events around the field kernel, each species' particle
         pass and each sort; 2: also around every single particle kernel."""

@@ -632,6 +632,36 @@ def test_launch_shape_does_not_change_results():
     assert kd >= 1 and ke >= 1 and ds[0].sync() == 0
 
 
+def test_pass_tuner_keeps_results_and_reports_candidates():
+    # the pass tuner times pipelined and unpipelined candidates on the
+    # discharge itself; the steps it takes are ordinary steps, so a discharge
+    # tuned along the way equals one stepped with the default schedule
+    from paper_2109_04469_amd import Discharge
+
+    w = workloads.scaled(workloads.get("c1_small"), 9000)
+    p = dict(w["params"], reflection=0.3, gamma_see=0.2, sort_interval=20)
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w, seed=22)
+    a, b = Discharge(p, xs), Discharge(p, xs)
+    for d in (a, b):
+        for sp in (0, 1):
+            d.set_state(sp, *init[sp], step=0)
+    res = a.tune_pass(steps_per_trial=12)
+    n = len(res["trials"])
+    assert n >= 4 and 0 <= res["best"] < n
+    assert {t["pipeline"] for t in res["trials"]} == {True, False}
+    assert all(t["us_per_step"] > 0.0 for t in res["trials"])
+    best = res["trials"][res["best"]]
+    assert best["us_per_step"] == min(t["us_per_step"] for t in res["trials"])
+    b.step(12 * n)
+    a.step(30)
+    b.step(30)
+    assert a.sync() == 0 and b.sync() == 0
+    for sp in (0, 1):
+        assert_state_equal(a.get_state(sp), b.get_state(sp), what=f"species {sp}")
+    assert np.array_equal(a.counters(), b.counters())
+
+
 def test_workgroups_taking_several_tiles_match_oracle():
     # More tiles than workgroups: 700,001 slots per species make 342 tiles of
     # 2048, against 256 workgroups at one per CU, so a workgroup takes two
