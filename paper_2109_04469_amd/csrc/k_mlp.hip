@@ -1,12 +1,16 @@
 // Kernels of the warm-start network: a plain MLP (GELU hidden layers, linear
 // output) with BF16 weights and FP32 accumulation, trained with Adam.
 //
-// The dense products run on the matrix cores: v_mfma_f32_32x32x8_bf16 takes
-// a 32x8 block of A and an 8x32 block of B, both rounded to BF16, and
-// accumulates the 32x32 product in FP32. A wave computes one 32x32 tile of
-// C; a workgroup of four waves a 64x64 tile. The operands are read straight
-// from global memory (the matrices are at most a few hundred kB and stay in
-// L2), with bounds checks, so any M, N, K work.
+// The dense products run on the matrix cores: v_mfma_f32_32x32x16_bf16
+// (gfx950) takes a 32x16 block of A and a 16x32 block of B, both rounded to
+// BF16, and accumulates the 32x32 product in FP32. A workgroup of four waves
+// computes a 64x64 tile of C, one 32x32 quarter per wave. K advances in
+// chunks of 32: the workgroup loads the chunk's 64x32 block of A and 32x64
+// block of B from global memory with consecutive threads on consecutive
+// addresses (along k or along m / n, whichever is contiguous), rounds them
+// to BF16 into LDS (rows of m or n, k contiguous), and each wave then reads
+// its fragments from LDS, 16 bytes per lane. Bounds are checked on the
+// loads, so any M, N, K and strides work.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -14,7 +18,8 @@
 
 namespace pic {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short short8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // FP32 -> BF16, round to nearest even (NaN kept quiet).
@@ -41,6 +46,39 @@ __device__ __forceinline__ float load_elem<uint16_t>(const uint16_t* p, int64_t 
   return from_bf16(p[i]);
 }
 
+constexpr int kGemmKC = 32;              // k per chunk
+constexpr int kGemmLd = kGemmKC + 8;      // LDS row length in BF16 (16-byte rows, padded)
+
+// One 64 x kGemmKC block of a matrix X(r, k) = X[r sr + k sk] into LDS rows
+// (r, k contiguous) as BF16, zero outside [0, R) x [0, K). 256 threads, 8
+// elements each; consecutive threads walk the contiguous dimension.
+template <typename T>
+__device__ __forceinline__ void stage_block(const T* __restrict__ X, int64_t sr, int64_t sk, int r0,
+                                            int k0, int R, int K, uint16_t* sX) {
+  const int tid = threadIdx.x;
+  if (sk == 1) {
+    // k contiguous: thread t takes row t / 4, k (t % 4) * 8 .. + 7
+    const int rr = tid >> 2, kk = (tid & 3) * 8;
+    const int r = r0 + rr;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = k0 + kk + q;
+      const float v = (r < R && k < K) ? load_elem<T>(X, (int64_t)r * sr + k) : 0.0f;
+      sX[rr * kGemmLd + kk + q] = to_bf16(v);
+    }
+  } else {
+    // r contiguous (or neither): thread t takes k t / 8, rows (t % 8) * 8 .. + 7
+    const int kk = tid >> 3, rb = (tid & 7) * 8;
+    const int k = k0 + kk;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = r0 + rb + q;
+      const float v = (r < R && k < K) ? load_elem<T>(X, (int64_t)r * sr + (int64_t)k * sk) : 0.0f;
+      sX[(rb + q) * kGemmLd + kk] = to_bf16(v);
+    }
+  }
+}
+
 // C[m][n] = sum_k A(m, k) B(k, n) with A(m, k) = A[m sam + k sak] (FP32) and
 // B(k, n) = B[k sbk + n sbn] (FP32 or BF16), both rounded to BF16 for the
 // product. Epilogue (ep):
@@ -54,31 +92,34 @@ __global__ __launch_bounds__(256) void k_gemm(const float* __restrict__ A, int64
                                               float* __restrict__ C, int64_t ldc,
                                               const float* __restrict__ bias, float* Z, int M, int N,
                                               int K) {
+  __shared__ __align__(16) uint16_t sA[64 * kGemmLd];  // rows m, k contiguous
+  __shared__ __align__(16) uint16_t sB[64 * kGemmLd];  // rows n, k contiguous
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
-  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
-  const int r = lane & 31;   // row of A / column of B this lane feeds
-  const int kq = lane >> 5;  // which four of the eight k of a step
+  const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int r = lane & 31;        // row of A / column of B this lane feeds
+  const int kh = (lane >> 5) * 8;  // which eight k of a 16-k step
   f32x16 acc = {};
-  for (int k0 = 0; k0 < K; k0 += 8) {
-    bf16x4 a, b;
+  for (int k0 = 0; k0 < K; k0 += kGemmKC) {
+    stage_block<float>(A, sam, sak, bm, k0, M, K, sA);
+    // B(k, n) as rows of n: X(n, k) = B[n sbn + k sbk]
+    stage_block<TB>(B, sbn, sbk, bn, k0, N, K, sB);
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = k0 + 4 * kq + q;
-      const int m = m0 + r, n = n0 + r;
-      const float av = (m < M && k < K) ? A[(int64_t)m * sam + (int64_t)k * sak] : 0.0f;
-      const float bv = (n < N && k < K) ? load_elem<TB>(B, (int64_t)k * sbk + (int64_t)n * sbn) : 0.0f;
-      a[q] = (short)to_bf16(av);
-      b[q] = (short)to_bf16(bv);
+    for (int ks = 0; ks < kGemmKC; ks += 16) {
+      const short8 a = *reinterpret_cast<const short8*>(&sA[(wm + r) * kGemmLd + ks + kh]);
+      const short8 b = *reinterpret_cast<const short8*>(&sB[(wn + r) * kGemmLd + ks + kh]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                    __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    __syncthreads();
   }
   // D[i][j]: lane j + 32 ((i / 4) % 2), register (i % 4) + 4 (i / 8)
-  const int n = n0 + (lane & 31);
+  const int n = bn + wn + (lane & 31);
 #pragma unroll
   for (int g = 0; g < 16; ++g) {
-    const int m = m0 + 8 * (g >> 2) + 4 * (lane >> 5) + (g & 3);
+    const int m = bm + wm + 8 * (g >> 2) + 4 * (lane >> 5) + (g & 3);
     if (m >= M || n >= N) continue;
     const int64_t o = (int64_t)m * ldc + n;
     float v = acc[g];
