@@ -56,10 +56,17 @@ BYTES_PER_PARTICLE_STEP = 64
 # and WRITE_SIZE (x1) at c3; a constant taken from the profile named below,
 # to be re-measured whenever the pass's kernels change (None when not
 # measured for the current kernels)
-PASS_TRAFFIC_BYTES_PER_PARTICLE = 60.15
-PASS_TRAFFIC_SOURCE = ("constant per electron particle-step from "
+PASS_TRAFFIC_BYTES_PER_PARTICLE = 47.4
+PASS_TRAFFIC_SOURCE = ("constant per electron particle-step of the pipelined pass from "
+                       "profiles/particle_pass_c3_first_steps_hbm_traffic.md and "
                        "profiles/particle_pass_c3_large_lowp_hbm_traffic.md (rocprofv3 FETCH_SIZE x2 + "
-                       "WRITE_SIZE over 20 steps after two RF cycles), times this window's particles")
+                       "WRITE_SIZE over 20 steps, after 5 steps and after two RF cycles), "
+                       "times this window's particles")
+# the same for the unpipelined pass (--pipeline off)
+PASS_TRAFFIC_BYTES_UNPIPELINED = 60.15
+PASS_TRAFFIC_SOURCE_UNPIPELINED = ("constant per electron particle-step of the unpipelined pass "
+                                   "(k_decide + k_emit + k_tail; rocprofv3 FETCH_SIZE x2 + WRITE_SIZE "
+                                   "over 20 steps after two RF cycles), times this window's particles")
 
 # the kernels the electron pass timer covers (per step, in launch order)
 PASS_KERNELS = ("electron particle pass: k_decide<0> + k_emit<0> + k_tail<0> (its queued slots, "
@@ -416,11 +423,12 @@ def main():
             avg_s = ems / en * 1e-3
             bytes_per_launch = BYTES_PER_PARTICLE_STEP * pe_w / en
             achieved = bytes_per_launch / avg_s / 1e9
-            traffic = (PASS_TRAFFIC_BYTES_PER_PARTICLE * pe_w / en
-                       if PASS_TRAFFIC_BYTES_PER_PARTICLE is not None else None)
+            piped = args.pipeline == "on"
+            tb = PASS_TRAFFIC_BYTES_PER_PARTICLE if piped else PASS_TRAFFIC_BYTES_UNPIPELINED
+            traffic = tb * pe_w / en if tb is not None else None
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                    "traffic_unit": "HBM bytes per launch", "traffic_source": PASS_TRAFFIC_SOURCE,
+                    "traffic_unit": "HBM bytes per launch", "traffic_source": (PASS_TRAFFIC_SOURCE if piped else PASS_TRAFFIC_SOURCE_UNPIPELINED),
                     "kernel": (PASS_KERNELS_PIPELINED if args.pipeline == "on" else PASS_KERNELS),
                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
                     "particles_per_launch": pe_w / en, "window_steps": steps}
