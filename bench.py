@@ -397,6 +397,12 @@ def main():
         kernels.update({k: {"launches": v[1], "us_per_launch": 1e3 * v[0] / v[1],
                             "note": "events around each kernel"}
                         for k, v in tk.items() if v[1] and k.split("_")[0] in ("e", "i")})
+        if tk.get("field", (0.0, 0))[1]:
+            # the next step's field inside the pass (k_field_cand on
+            # pipelined steps), events around each launch
+            v = tk["field"]
+            kernels["field_in_pass"] = {"launches": v[1], "us_per_launch": 1e3 * v[0] / v[1],
+                                        "note": "events around each kernel"}
         # the periodic cell sort: when the windows above hold none, step on
         # to the next sort with events around it, so its cost per step can
         # be stated (it is part of every step in the mean over a sort

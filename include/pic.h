@@ -393,7 +393,7 @@ typedef struct {
 int pic_tune_pass(pic_handle* h, int64_t steps_per_trial, pic_pass_trial* trials, int max_trials,
                   int* n_trials, int* best);
 
-/* Kernel timing with HIP events recorded on the handle's stream/* Kernel timing with HIP events recorded on the handle's stream
+/* Kernel timing with HIP events recorded on the handle's stream
  * (measurement surface). level 0: off. level 1: two event records around
  * the field kernel, each species' particle pass (PIC_TIMER_ELECTRON,
  * PIC_TIMER_ION: its decide, emit and rare kernels back to back, the gaps
