@@ -108,7 +108,8 @@ __device__ __forceinline__ i128p wave_incl_scan128(i128p v) {
   return v;
 }
 
-// Block-wide exclusive scan of one int64 per thread; returns the total.
+// Block-wide exclusive scan of one int64 per thread; returns the total. The
+// wave totals stay in s_wave: a caller that reuses it synchronises first.
 __device__ __forceinline__ int64_t block_excl_scan64(int64_t v, int64_t& excl, int64_t* s_wave) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -124,9 +125,7 @@ __device__ __forceinline__ int64_t block_excl_scan64(int64_t v, int64_t& excl, i
   }
   __syncthreads();
   excl = s_wave[wave] + inc - v;
-  const int64_t total = s_wave[kFieldWaves];
-  __syncthreads();
-  return total;
+  return s_wave[kFieldWaves];
 }
 
 __device__ __forceinline__ i128p block_excl_scan128(i128p v, i128p& excl, i128p* s_wave) {
@@ -151,22 +150,23 @@ __device__ __forceinline__ i128p block_excl_scan128(i128p v, i128p& excl, i128p*
   neg_v.lo = ~v.lo + 1;
   neg_v.hi = ~v.hi + (neg_v.lo == 0 ? 1 : 0);
   excl = add128(add128(s_wave[wave], inc), neg_v);
-  const i128p total = s_wave[kFieldWaves];
-  __syncthreads();
-  return total;
+  return s_wave[kFieldWaves];
 }
 
 // The whole field step, run by one workgroup of kFieldThreads threads.
+// Thread t takes the nodes [t per, (t + 1) per) (the last thread also any
+// node past them), per = ceil((N - 1) / threads): their deposits, rho, and
+// in the exact solve their scan elements, potentials and fields, so that
+// the exact solve needs no exchange through LDS beyond the two scans.
 __device__ __forceinline__ void field_block(const FieldArgs& a) {
-  __shared__ int64_t sC[kMaxNx];   // net deposit, then Q
   __shared__ double sRho[kMaxNx];
   __shared__ double sPhi[kMaxNx];
   __shared__ int64_t s_wave64[kFieldWaves + 1];
   __shared__ i128p s_wave128[kFieldWaves + 1];
-  __shared__ double sD0;
 
   const int tid = threadIdx.x;
   const int nx = a.nx;
+  const int m = nx - 1;  // scan elements 0..N-2
   if (tid == 0) {
     // stores and non-returning atomics: the first wave does not wait on a
     // read of the control block
@@ -174,46 +174,51 @@ __device__ __forceinline__ void field_block(const FieldArgs& a) {
     atomicAdd(&a.ctl->counters[C_STEPS], 1ull);
     if (a.measuring) atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctl->msteps), 1ull);
   }
-  // every deposit load of this thread in flight before the first use (one
-  // memory round trip instead of one per stride)
-  int64_t dep_e_v[kFieldPer], dep_i_v[kFieldPer];
+  constexpr int kOwn = kFieldPer + 1;
+  const int per = (m + kFieldThreads - 1) / kFieldThreads;
+  const int j0 = tid * per;
+  const int j1 = tid == kFieldThreads - 1 ? nx : min(j0 + per, nx);
+  // every deposit load of this thread in flight before the first use
+  int64_t c[kOwn];
+  double rho[kOwn];
+  {
+    int64_t de[kOwn], di[kOwn];
 #pragma unroll
-  for (int k = 0; k < kFieldPer; ++k) {
-    const int j = tid + k * kFieldThreads;
-    dep_e_v[k] = j < nx ? a.dep_e[j] : 0;
-    dep_i_v[k] = j < nx ? a.dep_i[j] : 0;
-  }
+    for (int q = 0; q < kOwn; ++q) {
+      const int j = j0 + q;
+      de[q] = j < j1 ? a.dep_e[j] : 0;
+      di[q] = j < j1 ? a.dep_i[j] : 0;
+    }
 #pragma unroll
-  for (int k = 0; k < kFieldPer; ++k) {
-    const int j = tid + k * kFieldThreads;
-    if (j >= nx) continue;
-    if (a.zero_a) a.zero_a[j] = 0;
-    if (a.zero_b) a.zero_b[j] = 0;
-    const int64_t de = dep_e_v[k];
-    const int64_t di = dep_i_v[k];
-    const int64_t c = di - de;
-    sC[j] = c;
-    double r = (double)c * a.qfac32;
-    const bool wall = (j == 0) || (j == nx - 1);
-    if (wall) r = 2.0 * r;  // half-cell volume at the electrodes
-    sRho[j] = r;
-    a.rho[j] = r;
-    if (a.measuring) {
-      double ne = (double)de * a.nfac32;
-      double ni = (double)di * a.nfac32;
-      if (wall) {
-        ne = 2.0 * ne;
-        ni = 2.0 * ni;
+    for (int q = 0; q < kOwn; ++q) {
+      const int j = j0 + q;
+      c[q] = di[q] - de[q];
+      rho[q] = 0.0;
+      if (j >= j1) continue;
+      if (a.zero_a) a.zero_a[j] = 0;
+      if (a.zero_b) a.zero_b[j] = 0;
+      double r = (double)c[q] * a.qfac32;
+      const bool wall = (j == 0) || (j == nx - 1);
+      if (wall) r = 2.0 * r;  // half-cell volume at the electrodes
+      rho[q] = r;
+      sRho[j] = r;
+      a.rho[j] = r;
+      if (a.measuring) {
+        double ne = (double)de[q] * a.nfac32;
+        double ni = (double)di[q] * a.nfac32;
+        if (wall) {
+          ne = 2.0 * ne;
+          ni = 2.0 * ni;
+        }
+        a.acc_ne[j] += ne;
+        a.acc_ni[j] += ni;
+        a.acc_w[j] += (double)de[q] * kInvTwo32;
       }
-      a.acc_ne[j] += ne;
-      a.acc_ni[j] += ni;
-      a.acc_w[j] += (double)de * kInvTwo32;
     }
   }
-  __syncthreads();
 
   if (a.mode == FIELD_ZERO || a.mode == FIELD_FIXED) {
-    for (int j = tid; j < nx; j += kFieldThreads) {
+    for (int j = j0; j < j1; ++j) {
       a.phi[j] = 0.0;
       if (a.mode == FIELD_ZERO) a.E[j] = 0.0;
     }
@@ -223,6 +228,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a) {
   const double dx = a.dx;
   const double V = a.V;
   if (a.mode == FIELD_THOMAS) {
+    __syncthreads();  // sRho complete
     // d_i = -(dx dx) rho_{i+1} / eps0 for the unknowns phi_1..phi_{N-2}
     const int n = nx - 2;
     for (int i = tid; i < n; i += kFieldThreads) sPhi[i + 1] = -(dx * dx) * sRho[i + 1] / kEps0;
@@ -264,70 +270,56 @@ __device__ __forceinline__ void field_block(const FieldArgs& a) {
   }
 
   // ---- exact integer prefix form ----------------------------------------
-  // c_0 = 0, c_k = C_k (k = 1..N-2); Q = inclusive scan of c over N-1 entries
-  const int m = nx - 1;
-  const int per = (m + kFieldThreads - 1) / kFieldThreads;
-  const int b0 = tid * per;
-  int64_t loc[kFieldPer];
+  // c_0 = 0, c_k = C_k (k = 1..N-2); Q = inclusive scan of c over N-1
+  // entries, R its exclusive scan. This thread's elements: its nodes below
+  // N-1.
+  int64_t loc[kOwn];  // local inclusive sums
   int64_t s = 0;
 #pragma unroll
-  for (int q = 0; q < kFieldPer; ++q) {
-    const int k = b0 + q;
-    int64_t c = 0;
-    if (q < per && k < m && k >= 1) c = sC[k];
-    s += c;
-    loc[q] = s;  // local inclusive
+  for (int q = 0; q < kOwn; ++q) {
+    const int k = j0 + q;
+    if (k < j1 && k < m && k >= 1) s += c[q];
+    loc[q] = s;
   }
-  int64_t excl;
-  block_excl_scan64(s, excl, s_wave64);
-  // Q_k = excl + loc[q]; R contributions: sum of own Q's
+  int64_t qb;  // Q before this thread's elements
+  block_excl_scan64(s, qb, s_wave64);
+  // R contributions: the sum of this thread's Q values
   i128p rsum = from64(0);
 #pragma unroll
-  for (int q = 0; q < kFieldPer; ++q) {
-    const int k = b0 + q;
-    if (q < per && k < m) {
-      const int64_t Qk = excl + loc[q];
-      loc[q] = Qk;
-      rsum = add128(rsum, from64(Qk));
-    }
-  }
-  i128p rexcl;
-  const i128p rtot = block_excl_scan128(rsum, rexcl, s_wave128);
-  // write Q into sC (after everyone has read C)
-#pragma unroll
-  for (int q = 0; q < kFieldPer; ++q) {
-    const int k = b0 + q;
-    if (q < per && k < m) sC[k] = loc[q];
-  }
-  if (tid == 0) sD0 = (a.kpois * to_double(rtot) - V) / (double)(nx - 1);
-  __syncthreads();
-  const double D0 = sD0;
+  for (int q = 0; q < kOwn; ++q)
+    if (j0 + q < j1 && j0 + q < m) rsum = add128(rsum, from64(qb + loc[q]));
+  i128p rb;  // R before this thread's elements
+  const i128p rtot = block_excl_scan128(rsum, rb, s_wave128);
+  // every thread has R_{N-1}: D0, then the potential phi_j = V + j D0 - K R_j
+  // and the field from D_j = D0 - K Q_j at its own nodes (Q_{j-1} of its
+  // first node is qb)
+  const double D0 = (a.kpois * to_double(rtot) - V) / (double)(nx - 1);
   const double K = a.kpois;
-  // potential: phi_j = V + j D0 - K R_j, R_j = sum_{i<j} Q_i
-  {
-    i128p r = rexcl;
+  i128p r = rb;
+  int64_t qprev = qb;
 #pragma unroll
-    for (int q = 0; q < kFieldPer; ++q) {
-      const int k = b0 + q;
-      if (q < per && k < m) {
-        a.phi[k] = V + (double)k * D0 - K * to_double(r);
-        r = add128(r, from64(loc[q]));
-      }
+  for (int q = 0; q < kOwn; ++q) {
+    const int j = j0 + q;
+    if (j >= j1) continue;
+    const int64_t qj = qb + loc[q];  // Q_j (j < N-1)
+    if (j < m) {
+      a.phi[j] = V + (double)j * D0 - K * to_double(r);
+      r = add128(r, from64(qj));
+    } else {
+      a.phi[j] = 0.0;
     }
-    if (tid == 0) a.phi[nx - 1] = 0.0;
-  }
-  for (int j = tid; j < nx; j += kFieldThreads) {
     double e;
     if (j == 0) {
-      e = -D0 / dx - sRho[0] * dx / (2.0 * kEps0);
+      e = -D0 / dx - rho[q] * dx / (2.0 * kEps0);
     } else if (j == nx - 1) {
-      const double Dlast = D0 - K * (double)sC[nx - 2];
-      e = -Dlast / dx + sRho[nx - 1] * dx / (2.0 * kEps0);
+      const double Dlast = D0 - K * (double)qprev;
+      e = -Dlast / dx + rho[q] * dx / (2.0 * kEps0);
     } else {
-      e = (K * (double)(sC[j - 1] + sC[j]) - 2.0 * D0) / (2.0 * dx);
+      e = (K * (double)(qprev + qj) - 2.0 * D0) / (2.0 * dx);
     }
     a.E[j] = e;
     if (!isfinite(e)) latch_error(a.ctl, kErrUnstable);
+    qprev = qj;
   }
 }
 
