@@ -637,8 +637,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
                                            int* jlo_out = nullptr, int* jhi_out = nullptr,
                                            uint32_t (*s_cand)[kCandWords] = nullptr,
                                            uint32_t* s_dcnt = nullptr, double* sE0 = nullptr,
-                                           int64_t* rq_range = nullptr,
-                                           const int64_t* pref = nullptr) {
+                                           int64_t* rq_range = nullptr) {
   constexpr bool FUSE = MODE >= 2;
   static_assert(!FUSE || SP == 0, "only electron passes decide the next step");
   const int tid = threadIdx.x;
@@ -648,12 +647,10 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
   const int par = a.parity;
   // outputs, births and queued slots of all earlier tiles (eight loads per
   // thread in flight at a time), and a's field staged into sE while the
-  // first of those loads are in flight; or, from pref, as the kernel before
-  // this one summed them (the tile loop's first barrier then orders the
-  // staged field before its use)
+  // first of those loads are in flight
   unsigned long long po = 0, pb = 0, pr = 0;
   bool staged = false;
-  for (int tb = 0; tb < (pref ? 0 : t0); tb += 8 * kBlock) {
+  for (int tb = 0; tb < t0; tb += 8 * kBlock) {
     uint64_t v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -674,26 +671,20 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
   }
   if (!staged && MODE != 1) stage_field<kBlock, STAGE_PER>(sE, FUSE ? b->E : a.E, a.nx);
   if (!staged && MODE == 3) stage_field<kBlock, STAGE_PER>(sE0, a.E, a.nx);
+  po = wave_sum<unsigned long long>(po);
+  pb = wave_sum<unsigned long long>(pb);
+  pr = wave_sum<unsigned long long>(pr);
+  if (lane == 0) {
+    s_red[0][wave] = po;
+    s_red[1][wave] = pb;
+    s_red[2][wave] = pr;
+  }
+  __syncthreads();
   int64_t prefO = 0, prefB = 0, prefR = 0;
-  if (pref) {
-    prefO = pref[0];
-    prefB = pref[1];
-    prefR = pref[2];
-  } else {
-    po = wave_sum<unsigned long long>(po);
-    pb = wave_sum<unsigned long long>(pb);
-    pr = wave_sum<unsigned long long>(pr);
-    if (lane == 0) {
-      s_red[0][wave] = po;
-      s_red[1][wave] = pb;
-      s_red[2][wave] = pr;
-    }
-    __syncthreads();
-    for (int w = 0; w < kBlock / kWave; ++w) {
-      prefO += (int64_t)s_red[0][w];
-      prefB += (int64_t)s_red[1][w];
-      prefR += (int64_t)s_red[2][w];
-    }
+  for (int w = 0; w < kBlock / kWave; ++w) {
+    prefO += (int64_t)s_red[0][w];
+    prefB += (int64_t)s_red[1][w];
+    prefR += (int64_t)s_red[2][w];
   }
 
   // MODE 2: this lane's deposit run (cell jr, weights of nodes jr, jr + 1);
@@ -1435,32 +1426,9 @@ __global__ __launch_bounds__(kBlock, EMIT_DECIDE_MIN_WAVES) void k_emit_decide(P
   if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
   if (tid == 0) s_dcnt[0] = s_dcnt[1] = 0u;
 
-  // contiguous runs, the longer ones (one tile more) on the lower workgroup
-  // indices: those are dispatched first on each CU, and the oldest waves of
-  // a CU are issued first, so they stream faster (measured: workgroups
-  // dispatched third on their CU took about 40 % longer per tile). The
-  // field kernel before this one wrote each workgroup's run, the prefix of
-  // the tile totals before it and the pass's counts (one load here instead
-  // of the counts and then the prefix); a launch on another grid works them
-  // out itself.
-  const bool have_rec = a.rec != nullptr && (int)gridDim.x == a.rec_grid;
-  int64_t n_tot, bbase;
-  int t0, t1;
-  int64_t pref[3];
-  if (have_rec) {
-    const WgRec& R = a.rec[blockIdx.x];
-    n_tot = uniform64(R.n_tot);
-    bbase = uniform64(R.bbase);
-    t0 = uniform32(R.t0);
-    t1 = uniform32(R.t1);
-    pref[0] = uniform64(R.pref_o);
-    pref[1] = uniform64(R.pref_b);
-    pref[2] = uniform64(R.pref_r);
-  } else {
-    n_tot = uniform64(ctl->n_e[par]);
-    if (n_tot > a.cap) n_tot = a.cap;  // the decide has latched the error
-    bbase = uniform64(ctl->n_i[par]);
-  }
+  int64_t n_tot = uniform64(ctl->n_e[par]);
+  if (n_tot > a.cap) n_tot = a.cap;  // the decide has latched the error
+  const int64_t bbase = uniform64(ctl->n_i[par]);
   const int ntiles = uniform32((int)((n_tot + kTile - 1) / kTile));
   if (ntiles == 0) {
     if (blockIdx.x == 0 && tid == 0) {
@@ -1469,12 +1437,14 @@ __global__ __launch_bounds__(kBlock, EMIT_DECIDE_MIN_WAVES) void k_emit_decide(P
     }
     return;
   }
-  if (!have_rec) {
-    const int g = (int)gridDim.x, b_ = (int)blockIdx.x;
-    const int q = ntiles / g, r = ntiles % g;
-    t0 = b_ < r ? b_ * (q + 1) : r * (q + 1) + (b_ - r) * q;
-    t1 = t0 + (b_ < r ? q + 1 : q);
-  }
+  // contiguous runs, the longer ones (one tile more) on the lower workgroup
+  // indices: those are dispatched first on each CU, and the oldest waves of
+  // a CU are issued first, so they stream faster (measured: workgroups
+  // dispatched third on their CU took about 40 % longer per tile)
+  const int g = (int)gridDim.x, b_ = (int)blockIdx.x;
+  const int q = ntiles / g, r = ntiles % g;
+  const int t0 = b_ < r ? b_ * (q + 1) : r * (q + 1) + (b_ - r) * q;
+  const int t1 = t0 + (b_ < r ? q + 1 : q);
   __syncthreads();  // sH, s_cnt, s_dcnt set
   if (t0 >= t1) return;
 
@@ -1482,8 +1452,7 @@ __global__ __launch_bounds__(kBlock, EMIT_DECIDE_MIN_WAVES) void k_emit_decide(P
   int64_t rq_range[3];
   emit_tiles<0, (kMaxNx + kBlock - 1) / kBlock, MODE>(a, t0, t1, 1, ntiles, n_tot, bbase, sE,
                                                       s_wtot, s_wr, s_ps, s_red, &b, sH, s_cnt,
-                                                      &jlo, &jhi, s_cand, s_dcnt, sE0, rq_range,
-                                                      have_rec ? pref : nullptr);
+                                                      &jlo, &jhi, s_cand, s_dcnt, sE0, rq_range);
   // this workgroup's queued slots and deferred decisions, their deposits
   // into the same LDS histogram
   const int64_t q0 = uniform64(rq_range[0]);

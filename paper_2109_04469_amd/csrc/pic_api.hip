@@ -48,7 +48,7 @@ double fedf_ion_emax(double rf_voltage_v) {
 
 struct Layout {
   size_t ctl, part[2][2][2], pid[2][2], pool[2][2][2], codes[2][2], tcnt[2][2], rq[2], dep_e[2], dep_i[2], rho, phi, E[2], cum[2], th_cp,
-      th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, fedf[2], sort_cnt, sort_seg, cand, dq, rec, total;
+      th_m, acc_ne, acc_ni, acc_w, acc_ew, eepf, fedf[2], sort_cnt, sort_seg, cand, dq, total;
   int64_t max_tiles[2];
   int sort_blocks;
 };
@@ -128,9 +128,6 @@ Layout make_layout(const pic_params* p, const pic_xsec* xs) {
   // candidacy bits of the electron slots of a pipelined step
   L.cand = take((size_t)((p->capacity[0] + 31) / 32 + 1) * sizeof(uint32_t));
   L.dq = take((size_t)p->capacity[0] * sizeof(uint32_t));
-  // where each workgroup of a fused electron pass starts (its grid is at
-  // most the tile count)
-  L.rec = take((size_t)L.max_tiles[0] * sizeof(WgRec));
   L.total = off;
   return L;
 }
@@ -467,13 +464,6 @@ StepPlan plan_step(pic_handle* h, bool field_ready, bool last, bool allow_fuse) 
     f.cand_step = q.ae_next.step;
     f.seed = h->p.seed;
     f.run = h->p.run;
-    // and where each workgroup of the fused kernel starts, for the grid it
-    // is launched with (the fused kernel checks it)
-    f.rec = h->rec;
-    f.rec_nion = &h->ctl->n_i[par];
-    f.rec_grid = q.e_pushed ? h->launch[0].grid_emit_decide : h->launch[0].grid_emit_decide3;
-    q.ae.rec = h->rec;
-    q.ae.rec_grid = f.rec_grid;
   }
   for (int sp = 0; sp < 2 && q.post; ++sp) {
     q.sa[sp] = sort_args(h, sp, q.post == 1);
@@ -791,7 +781,6 @@ int pic_init(const pic_params* p, const pic_xsec* xs, void* workspace, uint64_t 
   h->sort_seg = reinterpret_cast<uint32_t*>(w + L.sort_seg);
   h->cand = reinterpret_cast<uint32_t*>(w + L.cand);
   h->dq = reinterpret_cast<uint32_t*>(w + L.dq);
-  h->rec = reinterpret_cast<WgRec*>(w + L.rec);
   h->sort_blocks = L.sort_blocks;
   h->step = 0;
   h->cur[0] = h->cur[1] = 0;

@@ -20,21 +20,6 @@ constexpr double kKb = 1.380649e-23;
 
 enum FieldMode { FIELD_EXACT = 0, FIELD_ZERO = 1, FIELD_FIXED = 2, FIELD_THOMAS = 3 };
 
-// Where one workgroup of the fused electron kernel starts: its run of tiles
-// [t0, t1), the outputs, births and queued slots of all tiles before t0,
-// and the pass's slot count and ion count (written by the field kernel that
-// runs before it, for the grid it is launched with).
-struct alignas(16) WgRec {
-  int64_t pref_o;
-  int64_t pref_b;
-  int64_t pref_r;
-  int64_t n_tot;
-  int64_t bbase;
-  int32_t t0;
-  int32_t t1;
-  int64_t pad[2];
-};
-
 struct FieldArgs {
   const int64_t* dep_e;
   const int64_t* dep_i;
@@ -70,9 +55,6 @@ struct FieldArgs {
   uint32_t cand_step;
   uint32_t seed;
   uint32_t run;
-  WgRec* rec;               // the fused kernel's workgroup records (null: none written)
-  const int64_t* rec_nion;  // the ion count that kernel starts from
-  int rec_grid;             // the grid of that kernel
 };
 
 // Particle state of a species: x, v_x and a 4-byte pool index per slot in
@@ -105,8 +87,6 @@ struct PartArgs {
   uint8_t* codes;
   const uint32_t* cand;          // candidacy bit per slot (electrons, pipelined steps)
   uint32_t* dq;                  // output slots whose next-step decision is deferred
-  const WgRec* rec;              // per workgroup of a fused pass (null: computed in place)
-  int rec_grid;                  // the grid rec was written for
   double* acc_ew;                // CIC-weighted energy (electrons, measuring)
   unsigned long long* eepf;     // EEPF histogram (electrons, measuring)
   unsigned long long* fedf;     // this species' arrivals per energy bin, [wall][nbins]
@@ -329,7 +309,6 @@ struct pic_handle {
   uint32_t* sort_seg;
   uint32_t* cand;  // candidacy bits of a pipelined step's electron slots
   uint32_t* dq;    // slots of a pipelined step whose decisions are deferred
-  pic::WgRec* rec;  // workgroup records of a pipelined step's fused kernel
   int sort_blocks;
   // host-side schedule state
   int64_t step;
