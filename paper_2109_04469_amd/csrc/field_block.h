@@ -171,7 +171,7 @@ __device__ __forceinline__ void field_block(const FieldArgs& a) {
     // stores and non-returning atomics: the first wave does not wait on a
     // read of the control block
     a.ctl->ncodes[1] = 0;
-    atomicAdd(&a.ctl->counters[C_STEPS], 1ull);
+    count_add(a.ctl, C_STEPS, 1ull);
     if (a.measuring) atomicAdd(reinterpret_cast<unsigned long long*>(&a.ctl->msteps), 1ull);
   }
   constexpr int kOwn = kFieldPer + 1;

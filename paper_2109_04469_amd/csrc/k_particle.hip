@@ -516,14 +516,14 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
 
   if (blockIdx.x == 0 && tid == 0) {
     if (a.record) ctl->ncodes[SP] = n_push;
-    atomicAdd(&ctl->counters[SP == 0 ? C_E_PUSHED : C_I_PUSHED], (unsigned long long)n_push);
+    count_add(ctl, SP == 0 ? C_E_PUSHED : C_I_PUSHED, (unsigned long long)n_push);
   }
   __syncthreads();
 
   decide_tiles<SP, MEASURE>(a, blockIdx.x, ntiles, gridDim.x, n_push, n_tot, sE, sH, sEW,
                                    sEEPF, s_lo, s_hi, s_cnt);
 
-  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
+  if (tid < NCOUNTERS && s_cnt[tid]) count_add(ctl, tid, s_cnt[tid]);
   if (MEASURE) {
     for (int b = tid; b < a.nbins; b += kDB)
       if (sEEPF[b]) atomicAdd(&a.eepf[b], (unsigned long long)sEEPF[b]);
@@ -984,7 +984,7 @@ __device__ __forceinline__ void emit_tiles(const PartArgs& a, int t0, int t1, in
         // the next step pushes every output of this one
         const int64_t np = prefO < a.cap ? prefO : a.cap;
         if (b->record) ctl->ncodes[SP] = np;
-        atomicAdd(&ctl->counters[C_E_PUSHED], (unsigned long long)np);
+        count_add(ctl, C_E_PUSHED, (unsigned long long)np);
       }
     }
   }
@@ -1355,7 +1355,7 @@ __global__ __launch_bounds__(kBlock) void k_rare(PartArgs a) {
     rare_slot<SP, VAR, PUSHED>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
   }
   __syncthreads();
-  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
+  if (tid < NCOUNTERS && s_cnt[tid]) count_add(a.ctl, tid, s_cnt[tid]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1475,7 +1475,7 @@ __global__ __launch_bounds__(kBlock, EMIT_DECIDE_MIN_WAVES) void k_emit_decide(P
     const unsigned long long v = sH[j];
     if (v) atomicAdd(&b.dep_own[j], v);
   }
-  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&ctl->counters[tid], s_cnt[tid]);
+  if (tid < NCOUNTERS && s_cnt[tid]) count_add(ctl, tid, s_cnt[tid]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1505,7 +1505,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_tail(FieldArgs f, PartArgs a)
     rare_slot<SP, VAR, PUSHED>(a, s_cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);
   }
   __syncthreads();
-  if (tid < NCOUNTERS && s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
+  if (tid < NCOUNTERS && s_cnt[tid]) count_add(a.ctl, tid, s_cnt[tid]);
 }
 
 hipError_t launch_tail(int species, const FieldArgs& f, const PartArgs& a, int rare_blocks,
@@ -1601,7 +1601,7 @@ __global__ __launch_bounds__(kDB) void k_decide_b(const PartArgs* __restrict__ a
       const int64_t np = SP == 0 ? ctl->n_e[a.parity] : ctl->n_i[a.parity];
       if ((SP == 0 ? np : np + ctl->i_births) > a.cap) latch_error(ctl, kErrCapacity);
       if (a.record) ctl->ncodes[SP] = n_push;
-      atomicAdd(&ctl->counters[SP == 0 ? C_E_PUSHED : C_I_PUSHED], (unsigned long long)n_push);
+      count_add(ctl, SP == 0 ? C_E_PUSHED : C_I_PUSHED, (unsigned long long)n_push);
     }
   }
   block_exclusive<kDB>(tiles, n, s_ts, s_w);
@@ -1622,7 +1622,7 @@ __global__ __launch_bounds__(kDB) void k_decide_b(const PartArgs* __restrict__ a
                               sEEPF, s_lo, s_hi, s_cnt);
     // this discharge's event counts and EEPF counts
     if (tid < NCOUNTERS) {
-      if (s_cnt[tid]) atomicAdd(&a.ctl->counters[tid], s_cnt[tid]);
+      if (s_cnt[tid]) count_add(a.ctl, tid, s_cnt[tid]);
       s_cnt[tid] = 0ull;
     }
     if (MEASURE) {
@@ -1695,7 +1695,7 @@ __device__ __forceinline__ void rare_segments(const PartArgs* __restrict__ args,
     const int64_t rs = uniform64(s_rs[d]);
     const int64_t se = min(te, uniform64(s_rs[d + 1]));
     const int64_t bbase = uniform64(SP == 0 ? a.ctl->n_i[a.parity] : a.ctl->e_out);
-    unsigned long long* cnt = a.ctl->counters;
+    unsigned long long* cnt = a.ctl->counters[blockIdx.x % kCounterSlots];
     for (int64_t i = t + threadIdx.x; i < se; i += NT) {
       const uint4 q = a.rq[i - rs];
       rare_slot<SP, VAR>(a, cnt, (int64_t)q.x, q.y, (int64_t)q.z, (int64_t)q.w, bbase);

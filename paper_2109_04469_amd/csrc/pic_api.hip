@@ -1301,10 +1301,14 @@ int pic_get_monitors(pic_handle* h, pic_monitors* out) {
 
 int pic_get_counters(pic_handle* h, int64_t* counters) {
   if (!h || !counters) return PIC_EINVAL;
-  unsigned long long c[NCOUNTERS];
+  unsigned long long c[kCounterSlots][NCOUNTERS];
   HIP_TRY(hipMemcpyAsync(c, h->ctl->counters, sizeof(c), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
-  for (int i = 0; i < NCOUNTERS; ++i) counters[i] = (int64_t)c[i];
+  for (int i = 0; i < NCOUNTERS; ++i) {
+    unsigned long long t = 0;
+    for (int k = 0; k < kCounterSlots; ++k) t += c[k][i];
+    counters[i] = (int64_t)t;
+  }
   return latched(h);
 }
 

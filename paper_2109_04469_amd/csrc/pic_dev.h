@@ -42,6 +42,11 @@ enum Counter {
   C_REFLECT_LOST, C_BEYOND_TABLE, NCOUNTERS
 };
 
+// Copies of the event counters: a workgroup adds into copy blockIdx mod
+// kCounterSlots, so that the end-of-workgroup flushes of a large grid do not
+// all queue on one address; readers sum the copies.
+constexpr int kCounterSlots = 64;
+
 // Control block in device memory. Counts are double-buffered by step parity:
 // step n reads n_*[n & 1] and produces n_*[(n + 1) & 1].
 struct DevCtl {
@@ -54,7 +59,7 @@ struct DevCtl {
   int64_t n_rare[2];  // slots queued for the rare pass of the last step
   int64_t pool_n[2];  // velocity-pool entries in use (live + orphaned + new)
   int64_t pbase[2];   // first pool entry of the last pass's births, per pool
-  unsigned long long counters[NCOUNTERS];
+  alignas(128) unsigned long long counters[kCounterSlots][NCOUNTERS];  // one 128-byte line each
   // electrode diagnostics while measuring, [species][wall] (wall 0: x = 0)
   unsigned long long wall_hits[2][2];      // arrivals (reflected electrons included)
   unsigned long long wall_absorbed[2][2];  // of which absorbed
@@ -63,6 +68,11 @@ struct DevCtl {
   uint32_t err;
   uint32_t pad;
 };
+
+// Adds v to event counter i in this workgroup's copy.
+__device__ __forceinline__ void count_add(DevCtl* c, int i, unsigned long long v) {
+  atomicAdd(&c->counters[blockIdx.x % kCounterSlots][i], v);
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11).
