@@ -89,7 +89,7 @@ def quantities(runs, eepf_hi):
 
 
 def compare(runs_a, runs_b, eepf_hi=64, min_frac=0.99, f_quantile=0.999):
-    """The PAR-2 verdict for two ensembles: a report dictionary with
+    """The outcome of comparing two ensembles: a report dictionary with
     'ok' and, per quantity, the failing nodes and the Hotelling F against
     its percentile. eepf_hi: EEPF bins [0, eepf_hi) enter the bands (the
     populated part of the distribution)."""

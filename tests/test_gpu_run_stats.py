@@ -1,7 +1,7 @@
 """Run-level statistical parity of the GPU path with the oracle (Sec. 3.1:
 time-averaged density profiles of both species, the electron mean-energy
 profile and the EEPF at mid-gap), 8 GPU seeds (1-8) against 8 oracle seeds
-(101-108), by the procedure of tests/par2.py: per node or bin the Welch
+(101-108), by the procedure of tests/run_stats.py: per node or bin the Welch
 difference within the 3-sigma-equivalent Student-t bound on at least 99 %
 of them, and per quantity Hotelling's T^2 over coarse bands below its 99.9th
 percentile.
@@ -14,7 +14,7 @@ in worker processes while the GPU runs its ensemble as one batch."""
 import numpy as np
 import pytest
 
-import par2
+import run_stats
 from gpu_common import need_gpu
 from pic_inputs import state, workloads, xsec
 
@@ -68,12 +68,12 @@ CASES = {
 def test_ensemble_statistics_match_oracle(case):
     mk, warm, measured = CASES[case]
     w = mk()
-    print(f"[par2] {case}: oracle seeds 101-108 in workers, GPU seeds 1-8", flush=True)
-    pending = par2.oracle_ensemble_async(w, range(101, 109), warm, measured)
+    print(f"[run-stats] {case}: oracle seeds 101-108 in workers, GPU seeds 1-8", flush=True)
+    pending = run_stats.oracle_ensemble_async(w, range(101, 109), warm, measured)
     g = _gpu_ensemble(w, range(1, 9), warm, measured)
     o = pending.get(timeout=600)
-    rep = par2.compare(g, o)
-    print(f"[par2] {case}: node fraction {rep['node_fraction']:.4f}, "
+    rep = run_stats.compare(g, o)
+    print(f"[run-stats] {case}: node fraction {rep['node_fraction']:.4f}, "
           + ", ".join(f"{k} F {v['hotelling_f']:.2f} < {v['f_limit']:.2f}"
                       for k, v in rep.items() if isinstance(v, dict)), flush=True)
     assert rep["ok"], rep

@@ -1,4 +1,4 @@
-"""The run-level statistical comparison (tests/par2.py) on the CPU: its
+"""The run-level statistical comparison (tests/run_stats.py) on the CPU: its
 false-alarm rate on synthetic ensembles drawn from one distribution, its
 power against a shifted distribution, and the whole procedure on the oracle
 against itself with independent seeds, with and without a mistake planted
@@ -6,7 +6,7 @@ in the oracle's inputs (electron cross sections doubled, as a factor-2 slip
 in a table's units would do)."""
 import numpy as np
 
-import par2
+import run_stats
 from pic_inputs import workloads
 
 NX, NB = 129, 128
@@ -36,7 +36,7 @@ def _synthetic_runs(rng, n, shift=0.0):
 def test_false_alarm_rate_on_one_distribution():
     rng = np.random.default_rng(7)
     trials = 300
-    fails = sum(not par2.compare(_synthetic_runs(rng, 8), _synthetic_runs(rng, 8))["ok"]
+    fails = sum(not run_stats.compare(_synthetic_runs(rng, 8), _synthetic_runs(rng, 8))["ok"]
                 for _ in range(trials))
     # 5 Hotelling tests at 0.1 % each plus the 99 % node rule
     assert fails / trials < 0.03, fails
@@ -45,7 +45,7 @@ def test_false_alarm_rate_on_one_distribution():
 def test_power_against_a_shifted_profile():
     rng = np.random.default_rng(8)
     trials = 50
-    hits = sum(not par2.compare(_synthetic_runs(rng, 8), _synthetic_runs(rng, 8, shift=0.08))["ok"]
+    hits = sum(not run_stats.compare(_synthetic_runs(rng, 8), _synthetic_runs(rng, 8, shift=0.08))["ok"]
                for _ in range(trials))
     assert hits / trials > 0.9, hits
 
@@ -54,7 +54,7 @@ def test_node_rule_with_flat_columns():
     a = np.zeros((8, 3))
     b = np.zeros((8, 3))
     b[:, 2] = 1.0
-    ok = par2.node_test(a, b)
+    ok = run_stats.node_test(a, b)
     assert ok.tolist() == [True, True, False]
 
 
@@ -62,7 +62,7 @@ def test_hotelling_matches_univariate_t_squared():
     # with one band Hotelling's T^2 is the pooled two-sample t squared
     rng = np.random.default_rng(9)
     a, b = rng.normal(0, 1, (8, 1)), rng.normal(0.3, 1, (8, 1))
-    f, df = par2.hotelling_f(a, b)
+    f, df = run_stats.hotelling_f(a, b)
     from scipy import stats
 
     t = stats.ttest_ind(a[:, 0], b[:, 0], equal_var=True).statistic
@@ -78,10 +78,10 @@ def _small_c1():
 def test_oracle_against_itself_and_a_planted_mistake():
     w = _small_c1()
     warm, measured = 500, 1500
-    a = par2.oracle_ensemble_async(w, range(1, 9), warm, measured).get()
-    b = par2.oracle_ensemble_async(w, range(101, 109), warm, measured).get()
-    c = par2.oracle_ensemble_async(w, range(201, 209), warm, measured, xs_scale=2.0).get()
-    same = par2.compare(a, b)
+    a = run_stats.oracle_ensemble_async(w, range(1, 9), warm, measured).get()
+    b = run_stats.oracle_ensemble_async(w, range(101, 109), warm, measured).get()
+    c = run_stats.oracle_ensemble_async(w, range(201, 209), warm, measured, xs_scale=2.0).get()
+    same = run_stats.compare(a, b)
     assert same["ok"], same
-    planted = par2.compare(a, c)
+    planted = run_stats.compare(a, c)
     assert not planted["ok"], planted
