@@ -61,6 +61,14 @@ CASES = {
     "variants": dict(base="c1_small", n=7000, over=dict(
         reflection=0.2, gamma_see=0.2, ion_subcycle=2, sort_interval=11, pressure_pa=80.0,
         flags=RECORD | ANISO | OPAL)),
+    # the production-shaped discharge (512 cells, 50 Pa, 300 V, gamma 0.1)
+    "production_shape": dict(base="c2_production", n=20_000, over=dict(
+        sort_interval=13, flags=RECORD)),
+    # the largest grid (4096 cells): the fused kernel stages the field of
+    # both steps and its deposit histogram over 4097 nodes
+    "largest_grid": dict(base="c1_small", n=12_000, over=dict(
+        n_cells=4096, reflection=0.3, gamma_see=0.2, ion_subcycle=4, sort_interval=17,
+        pressure_pa=30.0, flags=RECORD)),
 }
 
 
