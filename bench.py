@@ -483,7 +483,8 @@ def main():
             "unit": "us of particle passes (electron + ion) per step, events around the passes",
             "trials": tuned["trials"], "choice": tuned["trials"][tuned["best"]],
             "note": "pipelined: fused emit-and-decide kernel at 1..3 workgroups per CU; unpipelined: "
-                    "separate decide and emit kernels at each decide shape, then each emit shape",
+                    "separate decide and emit kernels, the decide compiled for 512 and for 256 "
+                    "threads per workgroup at each of its shapes, then each emit shape",
         }
     out["warm_start"] = None
     if args.warm_start != "none":

@@ -358,6 +358,14 @@ int pic_set_launch(pic_handle* h, int decide_wg_per_cu, int emit_wg_per_cu);
  * only regroups its work across kernels). */
 int pic_set_pipeline(pic_handle* h, int on);
 
+/* Workgroup size of the decide kernels (both species): one of the compiled
+ * sizes, 512 threads (the default) or 256 threads; each takes the same tiles
+ * of 2048 slots, in runs of four consecutive slots per thread, so results do
+ * not depend on it. The decide workgroups per CU return to the most that
+ * fit at that size (pic_set_launch changes them). PIC_EINVAL for any other
+ * size. */
+int pic_set_decide_block(pic_handle* h, int threads);
+
 /* Picks the launch shape by measurement: advances the discharge by
  * steps_per_trial steps per candidate (every decide shape, then every emit
  * shape), timing the electron decide and emit kernels with events, and keeps
@@ -366,12 +374,14 @@ int pic_set_pipeline(pic_handle* h, int on);
 int pic_tune(pic_handle* h, int64_t steps_per_trial, int* decide_wg_per_cu, int* emit_wg_per_cu);
 
 /* One candidate configuration of the particle passes that pic_tune_pass
- * timed: the electron schedule (pic_set_pipeline), the launch shape
+ * timed: the electron schedule (pic_set_pipeline), the decide kernels'
+ * compiled workgroup size (pic_set_decide_block), the launch shape
  * (pic_set_launch) and the measured time of the particle passes (electron
  * and ion passes with their kernels back to back, PIC_TIMER_ELECTRON +
  * PIC_TIMER_ION) per step, microseconds. */
 typedef struct {
   int pipeline;
+  int decide_block;
   int decide_wg_per_cu;
   int emit_wg_per_cu;
   double us_per_step;
@@ -380,10 +390,12 @@ typedef struct {
 /* Chooses the particle passes' compiled kernels and launch shape by
  * measurement on the discharge itself: pipelined electron steps (the fused
  * emit-and-decide kernel) at each of its workgroups per CU, then unpipelined
- * steps (separate decide and emit kernels) at each decide shape and each
- * emit shape at the best decide shape. Each candidate advances the
+ * steps (separate decide and emit kernels) with the decide kernel at each
+ * compiled workgroup size (512 and 256 threads) and each of its shapes, then
+ * each emit shape at the best decide. Each candidate advances the
  * discharge by steps_per_trial ordinary steps with events around the
- * passes; the fastest is kept (pic_set_pipeline, pic_set_launch). trials: a
+ * passes; the fastest is kept (pic_set_pipeline, pic_set_decide_block,
+ * pic_set_launch). trials: a
  * caller-owned host array of max_trials entries (NULL with max_trials 0)
  * that receives the candidates in the order timed; n_trials: their count;
  * best: the index of the chosen one (both may be NULL). Results do not

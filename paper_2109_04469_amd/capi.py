@@ -70,7 +70,7 @@ _DP = ctypes.POINTER(ctypes.c_double)
 
 class PicPassTrial(ctypes.Structure):
     _fields_ = [
-        ("pipeline", ctypes.c_int), ("decide_wg_per_cu", ctypes.c_int),
+        ("pipeline", ctypes.c_int), ("decide_block", ctypes.c_int), ("decide_wg_per_cu", ctypes.c_int),
         ("emit_wg_per_cu", ctypes.c_int), ("us_per_step", ctypes.c_double),
     ]
 
@@ -144,6 +144,7 @@ def load():
     L.pic_get_monitors.argtypes = [P, ctypes.POINTER(PicMonitors)]
     L.pic_set_launch.argtypes = [P, ctypes.c_int, ctypes.c_int]
     L.pic_set_pipeline.argtypes = [P, ctypes.c_int]
+    L.pic_set_decide_block.argtypes = [P, ctypes.c_int]
     L.pic_tune.argtypes = [P, i64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.pic_tune_pass.argtypes = [P, i64, ctypes.POINTER(PicPassTrial), ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -161,7 +162,7 @@ def load():
     L.pic_selftest_copy.argtypes = [P, P, i64, P]
     for name in ("pic_workspace_bytes", "pic_init", "pic_set_state", "pic_get_state", "pic_step",
                  "pic_step_many", "pic_batch_workspace_bytes", "pic_batch_create", "pic_batch_step",
-                 "pic_load_profile", "pic_wall_moments", "pic_get_monitors", "pic_set_launch", "pic_set_pipeline", "pic_tune", "pic_tune_pass", "pic_mlp_workspace_bytes", "pic_mlp_init", "pic_mlp_num_params",
+                 "pic_load_profile", "pic_wall_moments", "pic_get_monitors", "pic_set_launch", "pic_set_pipeline", "pic_set_decide_block", "pic_tune", "pic_tune_pass", "pic_mlp_workspace_bytes", "pic_mlp_init", "pic_mlp_num_params",
                  "pic_mlp_set_params", "pic_mlp_get_params", "pic_mlp_forward", "pic_mlp_grad",
                  "pic_mlp_get_grad", "pic_mlp_get_loss", "pic_mlp_adam", "pic_mlp_train_step",
                  "pic_mlp_forward_static",

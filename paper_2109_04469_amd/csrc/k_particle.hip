@@ -142,12 +142,11 @@ __device__ __forceinline__ double cum_nu(const double* cum, int ntab, int p, dou
 // ---------------------------------------------------------------------------
 // k_decide
 
-#ifndef DECIDE_BLOCK
-#define DECIDE_BLOCK 512
-#endif
-constexpr int kDB = DECIDE_BLOCK;                // k_decide threads per workgroup
-constexpr int kDGroups = kTile / (4 * kDB);      // runs of four slots per thread per tile
-static_assert(kDGroups >= 1 && kTile % (4 * kDB) == 0, "a tile is whole runs of four slots");
+// k_decide's threads per workgroup: the default instance, and the other
+// compiled size (pic_set_decide_block), which takes the same tiles with
+// twice the runs of four slots per thread. The batched kernels use kDB.
+constexpr int kDB = kDecideBlocks[0];
+constexpr int kDBAlt = kDecideBlocks[1];
 
 // The wall model and the collision decision of one pushed slot whose new
 // position is not a finite point inside the gap, or that is a collision
@@ -285,7 +284,7 @@ __device__ __forceinline__ void decide_rare(const PartArgs& a, unsigned long lon
 // collect in LDS until one flush at the end. sH (and, measuring, sEW) are all
 // zero on entry and on exit; sE holds a's field; s_lo > s_hi on entry and on
 // exit, and the caller synchronises the workgroup before the next call.
-template <int SP, bool MEASURE>
+template <int SP, bool MEASURE, int DB = kDB>
 __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int t_end, int t_step,
                                              int64_t n_push, int64_t n_tot, const double* sE,
                                              unsigned long long* sH, double* sEW,
@@ -299,6 +298,9 @@ __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int
   const double L = a.L;
   const bool no_coll = a.no_coll != 0;
   const uint64_t cand_thr = no_coll ? 0ull : a.pcoll_thr;
+  // runs of four slots per thread per tile
+  constexpr int kDGroups = kTile / (4 * DB);
+  static_assert(kDGroups >= 1 && kTile % (4 * DB) == 0, "a tile is whole runs of four slots");
 
   int jlo = INT_MAX, jhi = -1;
   for (int t = t_begin; t < t_end; t += t_step) {
@@ -308,7 +310,7 @@ __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int
     // Philox block for the four candidacy draws, one 4-byte code store
 #pragma unroll
     for (int g = 0; g < kDGroups; ++g) {
-      const int64_t s0 = base + (int64_t)g * (4 * kDB) + 4 * tid;
+      const int64_t s0 = base + (int64_t)g * (4 * DB) + 4 * tid;
       if (s0 >= n_tot) continue;
       const bool full = s0 + 3 < n_tot;
       double xs[4], vxs[4];
@@ -443,7 +445,7 @@ __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int
   }
   __syncthreads();
   const int lo = s_lo, hi = s_hi;  // lo > hi when nothing was deposited
-  for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += kDB) {
+  for (int j = (lo <= hi ? lo : hi + 1) + tid; j <= hi; j += DB) {
     const unsigned long long v = sH[j];
     if (v) {
       atomicAdd(&a.dep_own[j], v);
@@ -466,14 +468,15 @@ __device__ __forceinline__ void decide_tiles(const PartArgs& a, int t_begin, int
 
 // Zeroes this workgroup's share of the tile totals buffer of the next pass
 // of discharge a (the previous pass of this species read it).
+template <int DB>
 __device__ __forceinline__ void clear_next_totals(const PartArgs& a) {
-  for (int64_t i = (int64_t)blockIdx.x * kDB + threadIdx.x; i < a.max_tiles;
-       i += (int64_t)gridDim.x * kDB)
+  for (int64_t i = (int64_t)blockIdx.x * DB + threadIdx.x; i < a.max_tiles;
+       i += (int64_t)gridDim.x * DB)
     a.tcnt_next[i] = 0ull;
 }
 
-template <int SP, bool MEASURE>
-__global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
+template <int SP, bool MEASURE, int DB = kDB>
+__global__ __launch_bounds__(DB) void k_decide(PartArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nx = a.nx;
   double* sE = reinterpret_cast<double*>(smem);
@@ -488,15 +491,15 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
   DevCtl* ctl = a.ctl;
   const int par = a.parity;
 
-  clear_next_totals(a);
+  clear_next_totals<DB>(a);
 
-  stage_field<kDB, (kMaxNx + kDB - 1) / kDB>(sE, a.E, nx);
-  for (int j = tid; j < nx; j += kDB) {
+  stage_field<DB, (kMaxNx + DB - 1) / DB>(sE, a.E, nx);
+  for (int j = tid; j < nx; j += DB) {
     sH[j] = 0ull;
     if (MEASURE) sEW[j] = 0.0;
   }
   if (MEASURE)
-    for (int b = tid; b < a.nbins; b += kDB) sEEPF[b] = 0u;
+    for (int b = tid; b < a.nbins; b += DB) sEEPF[b] = 0u;
   if (tid < NCOUNTERS) s_cnt[tid] = 0ull;
   if (tid == 0) {
     s_lo = INT_MAX;
@@ -520,12 +523,12 @@ __global__ __launch_bounds__(kDB) void k_decide(PartArgs a) {
   }
   __syncthreads();
 
-  decide_tiles<SP, MEASURE>(a, blockIdx.x, ntiles, gridDim.x, n_push, n_tot, sE, sH, sEW,
-                                   sEEPF, s_lo, s_hi, s_cnt);
+  decide_tiles<SP, MEASURE, DB>(a, blockIdx.x, ntiles, gridDim.x, n_push, n_tot, sE, sH,
+                                sEW, sEEPF, s_lo, s_hi, s_cnt);
 
   if (tid < NCOUNTERS && s_cnt[tid]) count_add(ctl, tid, s_cnt[tid]);
   if (MEASURE) {
-    for (int b = tid; b < a.nbins; b += kDB)
+    for (int b = tid; b < a.nbins; b += DB)
       if (sEEPF[b]) atomicAdd(&a.eepf[b], (unsigned long long)sEEPF[b]);
   }
 }
@@ -1760,17 +1763,21 @@ static size_t emit_decide_lds(int nx) { return (size_t)nx * 16; }
 
 PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, int64_t max_tiles) {
   PartLaunch c{};
+  c.max_tiles = max_tiles;
   for (int m = 0; m < 2; ++m) {
     c.lds_decide[m] = decide_lds(nx, m == 1, nbins);
-    int bpc;
-    if (species == 0)
-      bpc = m ? blocks_per_cu(k_decide<0, true>, c.lds_decide[m], kDB)
-              : blocks_per_cu(k_decide<0, false>, c.lds_decide[m], kDB);
-    else
-      bpc = blocks_per_cu(k_decide<1, false>, c.lds_decide[m], kDB);
-    c.grid_decide[m] = clamp_grid((int64_t)bpc * num_cu, max_tiles);
-    c.bpc_decide[m] = bpc;
+    const size_t l = c.lds_decide[m];
+    if (species == 0) {
+      c.bpc_decide_by[0][m] = m ? blocks_per_cu(k_decide<0, true, kDB>, l, kDB)
+                                : blocks_per_cu(k_decide<0, false, kDB>, l, kDB);
+      c.bpc_decide_by[1][m] = m ? blocks_per_cu(k_decide<0, true, kDBAlt>, l, kDBAlt)
+                                : blocks_per_cu(k_decide<0, false, kDBAlt>, l, kDBAlt);
+    } else {
+      c.bpc_decide_by[0][m] = blocks_per_cu(k_decide<1, false, kDB>, l, kDB);
+      c.bpc_decide_by[1][m] = blocks_per_cu(k_decide<1, false, kDBAlt>, l, kDBAlt);
+    }
   }
+  particle_launch_block(c, num_cu, kDB);
   c.lds_emit = emit_lds(nx);
   const int bpc = species == 0 ? blocks_per_cu(k_emit<0, 0>, c.lds_emit)
                                : blocks_per_cu(k_emit<1, 0>, c.lds_emit);
@@ -1783,8 +1790,18 @@ PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, in
       species == 0 ? blocks_per_cu(k_emit_decide<3, false>, c.lds_emit_decide + (size_t)nx * 8) : 1;
   c.grid_emit_decide3 = clamp_grid((int64_t)c.bpc_emit_decide3 * num_cu, max_tiles);
   c.grid_rare = num_cu * 2;
-  c.max_tiles = max_tiles;
   return c;
+}
+
+bool particle_launch_block(PartLaunch& c, int num_cu, int threads) {
+  if (threads != kDB && threads != kDBAlt) return false;
+  const int k = threads == kDB ? 0 : 1;
+  c.decide_block = threads;
+  for (int m = 0; m < 2; ++m) {
+    c.bpc_decide[m] = c.bpc_decide_by[k][m];
+    c.grid_decide[m] = clamp_grid((int64_t)c.bpc_decide[m] * num_cu, c.max_tiles);
+  }
+  return true;
 }
 
 void particle_launch_set(PartLaunch& c, int num_cu, int kd, int ke) {
@@ -1806,14 +1823,27 @@ hipError_t launch_particle_kernel(int kernel, int species, bool measure, const P
   const bool pushed = (flags & kLaunchPushed) != 0;
   if (species == 1 && pushed) return hipErrorInvalidValue;
   if (kernel == 0) {
-    const dim3 g(c.grid_decide[m]), t(kDB);
+    const dim3 g(c.grid_decide[m]);
     const size_t lds = c.lds_decide[m];
-    if (species == 1)
-      hipLaunchKernelGGL((k_decide<1, false>), g, t, lds, s, a);
-    else if (m)
-      hipLaunchKernelGGL((k_decide<0, true>), g, t, lds, s, a);
-    else
-      hipLaunchKernelGGL((k_decide<0, false>), g, t, lds, s, a);
+    if (c.decide_block == kDB) {
+      const dim3 t(kDB);
+      if (species == 1)
+        hipLaunchKernelGGL((k_decide<1, false, kDB>), g, t, lds, s, a);
+      else if (m)
+        hipLaunchKernelGGL((k_decide<0, true, kDB>), g, t, lds, s, a);
+      else
+        hipLaunchKernelGGL((k_decide<0, false, kDB>), g, t, lds, s, a);
+    } else if (c.decide_block == kDBAlt) {
+      const dim3 t(kDBAlt);
+      if (species == 1)
+        hipLaunchKernelGGL((k_decide<1, false, kDBAlt>), g, t, lds, s, a);
+      else if (m)
+        hipLaunchKernelGGL((k_decide<0, true, kDBAlt>), g, t, lds, s, a);
+      else
+        hipLaunchKernelGGL((k_decide<0, false, kDBAlt>), g, t, lds, s, a);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else if (kernel == 1) {
     const dim3 g(c.grid_emit), t(kBlock);
     if (species == 1)

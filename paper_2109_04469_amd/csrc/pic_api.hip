@@ -1335,6 +1335,13 @@ int pic_set_launch(pic_handle* h, int decide_wg_per_cu, int emit_wg_per_cu) {
   return PIC_OK;
 }
 
+int pic_set_decide_block(pic_handle* h, int threads) {
+  if (!h || (threads != kDecideBlocks[0] && threads != kDecideBlocks[1])) return PIC_EINVAL;
+  for (int s = 0; s < 2; ++s)
+    if (!particle_launch_block(h->launch[s], h->num_cu, threads)) return PIC_EINVAL;
+  return PIC_OK;
+}
+
 int pic_set_pipeline(pic_handle* h, int on) {
   if (!h || on < 0 || on > 1) return PIC_EINVAL;
   h->pipeline = on;
@@ -1426,13 +1433,16 @@ int pic_tune_pass(pic_handle* h, int64_t steps_per_trial, pic_pass_trial* trials
     return PIC_OK;
   };
   const PartLaunch& c = h->launch[0];
+  const int db0 = c.decide_block;
   int n = 0, ib = -1;
   pic_pass_trial bestt{};
-  auto run = [&](int pipe, int kd, int ke, double* us) -> int {
+  auto run = [&](int pipe, int db, int kd, int ke, double* us) -> int {
     h->pipeline = pipe;
-    pic_set_launch(h, kd, ke);
-    pic_pass_trial t{pipe, kd, ke, 0.0};
-    const int st = trial(&t.us_per_step);
+    int st = pic_set_decide_block(h, db);
+    if (!st) st = pic_set_launch(h, kd, ke);
+    if (st) return st;
+    pic_pass_trial t{pipe, db, kd, ke, 0.0};
+    st = trial(&t.us_per_step);
     if (st) return st;
     if (n < max_trials) trials[n] = t;
     if (ib < 0 || t.us_per_step < bestt.us_per_step) {
@@ -1446,25 +1456,32 @@ int pic_tune_pass(pic_handle* h, int64_t steps_per_trial, pic_pass_trial* trials
   int st = PIC_OK;
   double us = 0.0;
   // pipelined: the fused emit's workgroups per CU (its decide pass runs only
-  // on the steps that cannot be pipelined, at the most that fit)
-  const int kd_max = c.bpc_decide[0];
-  for (int k = 1; k <= c.bpc_emit_decide && !st; ++k) st = run(1, kd_max, k, &us);
-  // unpipelined: each decide shape, then each emit shape at the best decide
-  int kd_best = kd_max;
+  // on the steps that cannot be pipelined, at the default size and the most
+  // workgroups that fit)
+  const int kd_max = c.bpc_decide_by[0][0];
+  for (int k = 1; k <= c.bpc_emit_decide && !st; ++k) st = run(1, kDecideBlocks[0], kd_max, k, &us);
+  // unpipelined: each compiled decide size at each of its shapes, then each
+  // emit shape at the best decide
+  int db_best = kDecideBlocks[0], kd_best = kd_max;
   double kd_us = -1.0;
-  for (int k = 1; k <= kd_max && !st; ++k) {
-    st = run(0, k, c.bpc_emit, &us);
-    if (!st && (kd_us < 0.0 || us < kd_us)) {
-      kd_us = us;
-      kd_best = k;
+  for (int b = 0; b < 2 && !st; ++b) {
+    for (int k = 1; k <= c.bpc_decide_by[b][0] && !st; ++k) {
+      st = run(0, kDecideBlocks[b], k, c.bpc_emit, &us);
+      if (!st && (kd_us < 0.0 || us < kd_us)) {
+        kd_us = us;
+        db_best = kDecideBlocks[b];
+        kd_best = k;
+      }
     }
   }
-  for (int k = 1; k < c.bpc_emit && !st; ++k) st = run(0, kd_best, k, &us);
+  for (int k = 1; k < c.bpc_emit && !st; ++k) st = run(0, db_best, kd_best, k, &us);
   if (st) {
     h->pipeline = pipeline0;
+    (void)pic_set_decide_block(h, db0);
     return st;
   }
   h->pipeline = bestt.pipeline;
+  pic_set_decide_block(h, bestt.decide_block);
   pic_set_launch(h, bestt.decide_wg_per_cu, bestt.emit_wg_per_cu);
   if (n_trials) *n_trials = n;
   if (best) *best = ib;

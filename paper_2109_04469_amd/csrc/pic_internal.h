@@ -160,6 +160,9 @@ hipError_t launch_field(const FieldArgs& a, hipStream_t s);
 // electron slots (the other workgroups)
 hipError_t launch_field_cand(const FieldArgs& a, int num_cu, hipStream_t s);
 // grid and LDS bytes of one species' two particle kernels
+// Compiled workgroup sizes of k_decide, the default first.
+constexpr int kDecideBlocks[2] = {512, 256};
+
 struct PartLaunch {
   int grid_decide[2];  // [measuring]
   size_t lds_decide[2];
@@ -171,6 +174,8 @@ struct PartLaunch {
   int bpc_emit_decide3;
   int grid_rare;
   int bpc_decide[2];   // resident workgroups per CU at these LDS sizes (occupancy)
+  int decide_block;    // k_decide's threads per workgroup: one of its compiled sizes
+  int bpc_decide_by[2][2];  // [default size, other size][measuring]: occupancy of each
   int bpc_emit;
   int bpc_emit_decide;
   int64_t max_tiles;
@@ -179,6 +184,9 @@ PartLaunch particle_launch_config(int species, int nx, int nbins, int num_cu, in
 // the same with k_decide at kd and k_emit at ke workgroups per CU (clamped
 // to [1, occupancy] and to the tile count)
 void particle_launch_set(PartLaunch& c, int num_cu, int kd, int ke);
+// k_decide compiled for `threads` per workgroup (512 or 256), at the most
+// workgroups per CU that fit; false (nothing changed) for any other size
+bool particle_launch_block(PartLaunch& c, int num_cu, int threads);
 // kernel 0: k_decide, 1: k_emit, 2: k_rare (launched in this order).
 // flags (electrons only): kLaunchPushed, the emit and rare kernels take an
 // input that holds the pushed state (the previous step's fused emit decided

@@ -219,6 +219,10 @@ class Discharge:
     def set_pipeline(self, on=True):
         check(self.L.pic_set_pipeline(self.h, 1 if on else 0), "pic_set_pipeline")
 
+    def set_decide_block(self, threads):
+        """Decide kernels' workgroup size: 512 (default) or 256 threads."""
+        check(self.L.pic_set_decide_block(self.h, int(threads)), "pic_set_decide_block")
+
     def tune(self, steps_per_trial=100):
         """Measures the particle kernels' launch shapes on this discharge
         (advancing it) and keeps the fastest; returns (decide, emit)
@@ -232,15 +236,16 @@ class Discharge:
         """Times the particle passes' candidate schedules and launch shapes on
         this discharge (advancing it by steps_per_trial steps per candidate)
         and keeps the fastest; returns {"trials": [...], "best": index}, each
-        trial a dict of pipeline, decide_wg_per_cu, emit_wg_per_cu and
-        us_per_step."""
+        trial a dict of pipeline, decide_block, decide_wg_per_cu,
+        emit_wg_per_cu and us_per_step."""
         from .capi import PicPassTrial
 
         arr = (PicPassTrial * 32)()
         n, best = ctypes.c_int(), ctypes.c_int()
         check(self.L.pic_tune_pass(self.h, int(steps_per_trial), arr, 32, ctypes.byref(n),
                                    ctypes.byref(best)), "pic_tune_pass")
-        trials = [{"pipeline": bool(t.pipeline), "decide_wg_per_cu": t.decide_wg_per_cu,
+        trials = [{"pipeline": bool(t.pipeline), "decide_block": t.decide_block,
+                   "decide_wg_per_cu": t.decide_wg_per_cu,
                    "emit_wg_per_cu": t.emit_wg_per_cu, "us_per_step": t.us_per_step}
                   for t in arr[:min(n.value, 32)]]
         return {"trials": trials, "best": best.value}

@@ -608,19 +608,22 @@ def test_method_variants_single_step_match_oracle():
 
 
 def test_launch_shape_does_not_change_results():
-    # grid sizes change which workgroup takes which tile, never a result
-    from paper_2109_04469_amd import Discharge
+    # grid sizes and the decide kernels' compiled workgroup size (512 or 256
+    # threads) change which workgroup and thread take which slots, never a
+    # result; 30,001 slots per species make 15 tiles, the last one ragged
+    from paper_2109_04469_amd import Discharge, PicError
 
-    w = workloads.scaled(workloads.get("c1_small"), 9000)
+    w = workloads.scaled(workloads.get("c1_small"), 30_001)
     p = dict(w["params"], reflection=0.3, gamma_see=0.2, sort_interval=20)
     xs = xsec.argon_synthetic()
     init = state.initial_state(w, seed=21)
     ds = []
-    for shape in ((1, 1), (3, 4), (2, 3)):
+    for block, kd, ke in ((512, 1, 1), (512, 3, 4), (512, 2, 3), (256, 1, 2), (256, 8, 4)):
         d = Discharge(p, xs)
         for sp in (0, 1):
             d.set_state(sp, *init[sp], step=0)
-        d.set_launch(*shape)
+        d.set_decide_block(block)
+        d.set_launch(kd, ke)
         d.step(60)
         assert d.sync() == 0
         ds.append(d)
@@ -630,6 +633,9 @@ def test_launch_shape_does_not_change_results():
         assert np.array_equal(d.counters(), ds[0].counters())
     kd, ke = ds[0].tune(10)
     assert kd >= 1 and ke >= 1 and ds[0].sync() == 0
+    for bad in (0, 128, 384, 1024):
+        with pytest.raises(PicError):
+            ds[0].set_decide_block(bad)
 
 
 def test_pass_tuner_keeps_results_and_reports_candidates():
@@ -650,6 +656,7 @@ def test_pass_tuner_keeps_results_and_reports_candidates():
     n = len(res["trials"])
     assert n >= 4 and 0 <= res["best"] < n
     assert {t["pipeline"] for t in res["trials"]} == {True, False}
+    assert {t["decide_block"] for t in res["trials"] if not t["pipeline"]} == {512, 256}
     assert all(t["us_per_step"] > 0.0 for t in res["trials"])
     best = res["trials"][res["best"]]
     assert best["us_per_step"] == min(t["us_per_step"] for t in res["trials"])
@@ -662,12 +669,14 @@ def test_pass_tuner_keeps_results_and_reports_candidates():
     assert np.array_equal(a.counters(), b.counters())
 
 
-def test_workgroups_taking_several_tiles_match_oracle():
+@pytest.mark.parametrize("decide_block", [512, 256])
+def test_workgroups_taking_several_tiles_match_oracle(decide_block):
     # More tiles than workgroups: 700,001 slots per species make 342 tiles of
     # 2048, against 256 workgroups at one per CU, so a workgroup takes two
     # tiles (the ion emit carries its prefix over the tiles in between), and
     # the last tile is ragged. The default shape (one tile per workgroup) and
-    # the oracle must agree with it.
+    # the oracle must agree with it, with the decide kernels compiled for
+    # either workgroup size.
     from paper_2109_04469_amd import Discharge
 
     w = workloads.scaled(workloads.get("c1_small"), 700_001)
@@ -676,6 +685,7 @@ def test_workgroups_taking_several_tiles_match_oracle():
     init = state.initial_state(w, seed=33)
     L = p["gap_m"]
     gpu, ora = pair(p, xs, init)
+    gpu.set_decide_block(decide_block)
     gpu.set_launch(1, 1)
     ref = Discharge(p, xs, "cuda:0")
     for sp in (0, 1):
