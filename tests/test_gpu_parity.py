@@ -334,6 +334,33 @@ def test_capacity_overflow_is_reported():
     assert d.sync() == -3
 
 
+@pytest.mark.parametrize("pipeline", [True, False])
+def test_capacity_overflow_in_multi_step_calls_is_reported(pipeline):
+    # The same overflow inside a call of several steps with sub-cycled ions,
+    # so that (pipelined) the fused emit-and-decide kernel and the queued
+    # slots it runs meet outputs, births and pool entries beyond the
+    # capacities on every step after the first: the writes past them are
+    # dropped and the error stays latched, so the state is not handed out.
+    w = workloads.scaled(workloads.get("c1_small"), 2000)
+    p = dict(w["params"], capacity=(2000, 4000), pressure_pa=300.0, ion_subcycle=4,
+             sort_interval=0)
+    xs = xsec.argon_synthetic()
+    L = p["gap_m"]
+    e = state.maxwellian_uniform(2000, L, 50.0, 0, 3)
+    i = state.maxwellian_uniform(2000, L, 0.03, 1, 3)
+    from paper_2109_04469_amd import Discharge, PicError
+
+    d = Discharge(p, xs)
+    d.set_pipeline(pipeline)
+    d.set_state(0, *e, step=0)
+    d.set_state(1, *i, step=0)
+    d.step(7)
+    assert d.sync() == -3
+    with pytest.raises(PicError):
+        d.get_state(0)
+    assert d.sync() == -3
+
+
 def test_timing_levels():
     w = workloads.scaled(workloads.get("c1_small"), 4000)
     p = dict(w["params"], ion_subcycle=5)
