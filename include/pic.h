@@ -363,7 +363,8 @@ int pic_set_pipeline(pic_handle* h, int on);
  * of 2048 slots, in runs of four consecutive slots per thread, so results do
  * not depend on it. The decide workgroups per CU return to the most that
  * fit at that size (pic_set_launch changes them). PIC_EINVAL for any other
- * size. */
+ * size. Steps taken through a batch (pic_batch_step) use the
+ * batched kernels, whose size is fixed at 512. */
 int pic_set_decide_block(pic_handle* h, int threads);
 
 /* Picks the launch shape by measurement: advances the discharge by
