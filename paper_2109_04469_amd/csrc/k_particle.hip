@@ -32,6 +32,17 @@
 // parent; births of the other species (Ar+ from ionization, secondary
 // electrons from ion impact) are appended after that species' particles in
 // parent-slot order.
+//
+// Pipelined electron steps (pic_set_pipeline) replace k_decide of step n+1:
+//   k_emit_decide  is k_emit of step n that also decides step n+1 for each
+//             output (the push with the next field staged in LDS, the
+//             candidacy bit k_field_cand drew, and for the few outputs that
+//             leave the gap or are candidates the wall and process decisions),
+//             writing the next step's decision codes, tile totals and
+//             deposit; each workgroup then runs its own queued slots of step n
+//             and the decisions it deferred, one item per thread.
+// The arithmetic of every decision is the same in all kernels, so pipelined
+// and unpipelined steps give identical results.
 #include <climits>
 
 #include "field_block.h"
