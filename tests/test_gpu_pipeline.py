@@ -132,3 +132,34 @@ def test_pipelined_large_workload_equals_single_steps():
     for _ in range(23):
         single.step(1)
     _same(many, single, "c3 23 steps")
+
+
+@pytest.mark.parametrize("empty", [0, 1])
+def test_pipelined_steps_from_an_empty_species(empty):
+    # no electrons at the start (ion impacts emit the first ones) or no ions
+    # (ionizations make the first ones): the fused kernel and the candidacy
+    # draw meet empty passes and then the first particles of a species;
+    # calls of several steps against single steps, bit for bit. (Without
+    # ions the electrons' own space charge heats them within tens of steps;
+    # the pressure, the step count and the capacities keep the ionization
+    # growth inside the arrays.)
+    w = workloads.scaled(workloads.get("c1_small"), 6000, capacity_factor=8)
+    p = dict(w["params"], reflection=0.2, gamma_see=0.4, ion_subcycle=3, sort_interval=0,
+             pressure_pa=20.0, rf_voltage_v=150.0, flags=RECORD)
+    xs = xsec.argon_synthetic()
+    L = p["gap_m"]
+    dt = 1.0 / (p["rf_freq_hz"] * p["steps_per_cycle"])
+    ve, vi = _vth(8.0, ME), _vth(20.0, MAR)
+    init = {0: near_wall_state(6000, L, ve, ve * dt, 5, 0),
+            1: near_wall_state(6000, L, vi, vi * dt * p["ion_subcycle"], 5, 1)}
+    z = np.zeros(0)
+    init[empty] = (z, z, z, z)
+    many, single = _pair(p, xs, init)
+    many.set_pipeline(True)
+    for k, n in enumerate((1, 7, 22)):
+        print(f"[pipeline] empty species {empty}: call {k} of {n} steps", flush=True)
+        many.step(n)
+        for _ in range(n):
+            single.step(1)
+        _same(many, single, f"empty species {empty}, after call {k}")
+    assert many.count(empty) > 0, "the empty species gained particles"
