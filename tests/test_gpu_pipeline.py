@@ -163,3 +163,23 @@ def test_pipelined_steps_from_an_empty_species(empty):
             single.step(1)
         _same(many, single, f"empty species {empty}, after call {k}")
     assert many.count(empty) > 0, "the empty species gained particles"
+
+
+def test_pipelined_steps_with_the_smaller_decide_workgroups():
+    # the decide kernels compiled for 256 threads feed the fused kernel on
+    # the steps that cannot be pipelined (the first of a call, after ion
+    # steps); against single steps with the default 512-thread decide
+    w = workloads.scaled(workloads.get("c1_small"), 30_001)
+    p = dict(w["params"], reflection=0.3, gamma_see=0.2, ion_subcycle=4, sort_interval=19,
+             pressure_pa=30.0, flags=RECORD)
+    xs = xsec.argon_synthetic()
+    init = state.initial_state(w, seed=14)
+    many, single = _pair(p, xs, init)
+    many.set_pipeline(True)
+    many.set_decide_block(256)
+    for k, n in enumerate((3, 41)):
+        print(f"[pipeline] 256-thread decide: call {k} of {n} steps", flush=True)
+        many.step(n)
+        for _ in range(n):
+            single.step(1)
+        _same(many, single, f"256-thread decide, after call {k}")
