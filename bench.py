@@ -73,9 +73,9 @@ PASS_KERNELS = ("electron particle pass: k_decide<0> + k_emit<0> + k_tail<0> (it
                 "overlapped with the next step's field); k_rare<0> instead of k_tail on ion steps")
 PASS_KERNELS_PIPELINED = (
     "electron particle pass, pipelined: k_field_cand (next step's field and candidacy bits) + "
-    "k_emit_decide<0> (this step's emit, the next step's decisions, this step's queued slots); "
-    "on ion steps k_emit<0> + k_rare<0>, on the step after one k_decide<0> + k_field_cand + "
-    "k_emit_decide<0>")
+    "k_emit_decide<2> (this step's emit, the next step's decisions, this step's queued slots); "
+    "on ion steps k_emit<0, 1> + k_rare<0>, on the step after one and the first of a call "
+    "k_decide<0> + k_field_cand + k_emit_decide<3> (the emit pushes again)")
 
 DESCRIPTIONS = {
     "c3_large_lowp": ("gap 6.7 cm, 2048 cells, dt=T_RF/8000, 13.56 MHz, 500 V, 2 Pa, gamma 0.2, R 0.5, "
